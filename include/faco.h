@@ -1,0 +1,173 @@
+/*
+ * faco.h -- C ABI of the MI355X Focused ACO (FACO) library.
+ *
+ * Method: R. Skinderowicz, "Improving Ant Colony Optimization Efficiency for
+ * Solving Large TSP Instances" (Applied Soft Computing 2022, arXiv 2203.02228).
+ *
+ * Problem (Sec. 2.1): n cities 0..n-1 with symmetric positive costs; find a
+ * minimum-cost Hamiltonian cycle.  Here the cost is TSPLIB EUC_2D,
+ * nint(sqrt(dx^2 + dy^2)), on integer coordinates.  The result is a
+ * permutation of 0..n-1 (the tour) and its integer cost.
+ *
+ * One call of faco_run_iterations advances the main loop of Alg. 2: every ant
+ * builds a focused tour (Eq. (1) choice over candidate/backup lists until
+ * min_new_edges edges differ from the source solution, remainder copied from
+ * the source), improves it with the checklist local search of Alg. 3 (plus
+ * Or-opt), then the colony picks the iteration best, updates the global best
+ * and the trail limits (Sec. 4.5), chooses the next source and applies the
+ * bounded pheromone update of Eq. (2).
+ *
+ * All state lives in device memory owned by the library.  Every call returns
+ * FACO_OK (0) or a negative FACO_E* code; the message is available from
+ * faco_last_error().  Distinct handles may be used from distinct host threads
+ * concurrently; one handle must not be used by two threads at once.
+ */
+#ifndef FACO_H
+#define FACO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FACO_OK 0
+#define FACO_EINVAL (-1)  /* invalid argument                           */
+#define FACO_EDUP (-2)    /* two cities share coordinates (zero cost)   */
+#define FACO_ENOMEM (-3)  /* device or host allocation failed           */
+#define FACO_EDEVICE (-4) /* HIP runtime / kernel launch error          */
+
+/* local-search bits of faco_params.ls_flags */
+#define FACO_LS_2OPT 1u  /* 2-opt moves of Alg. 3                         */
+#define FACO_LS_OROPT 2u /* Or-opt segment insertion (not in the paper)   */
+#define FACO_LS_SWEEP 4u /* re-examine every listed node until none improves */
+
+/* Parameters (Table 1 of the paper; names follow it). */
+typedef struct faco_params {
+  int32_t cl_size;       /* candidate-list length (paper: 16); >= 2          */
+  int32_t bl_size;       /* backup-list length (paper: 64); 0..64            */
+  int32_t n_ants;        /* ants per iteration; 1..4096                       */
+  int32_t min_new_edges; /* new edges before copying (paper: 8); >= 0        */
+  float rho;             /* pheromone retention of Eq. (2); [0, 1)            */
+  float reserved0;       /* must be 0                                         */
+  double p_best;         /* Sec. 4.5 limit parameter; (0, 1); e.g. 0.05       */
+  double p_source_gbest; /* probability that the source is the global best
+                            (paper: 0.01, Sec. 5.3); [0, 1]                   */
+  uint64_t seed;         /* Philox4x64-10 key word 0                          */
+  uint32_t ls_flags;     /* FACO_LS_* bits                                    */
+  int32_t oropt_max_seg; /* longest Or-opt segment; 1..3                      */
+} faco_params;
+
+typedef struct faco_instance faco_instance;
+
+/*
+ * Build an instance (Alg. 2 before the main loop): candidate lists (cl_size
+ * nearest cities by exact squared distance, ties by id) and backup lists (the
+ * next bl_size), heuristic eta = 1/d, the initial solution (nearest neighbour
+ * from city 0 improved by the local search over all cities), the trail limits,
+ * tau = tau_max everywhere, source = initial solution.
+ *   xy         host pointer, n rows of (x, y) int32, row-major; each
+ *              coordinate in [0, 2^23).  Copied; the caller keeps ownership.
+ *   n          number of cities, 4 .. 2^24.
+ *   p          parameters, copied.
+ *   hip_stream hipStream_t to run on (NULL = the default stream).  The handle
+ *              keeps using this stream for all later calls.
+ *   out        receives the new handle on success.
+ * Runs asynchronously on the stream but returns after setup has finished.
+ * Errors: FACO_EINVAL, FACO_EDUP, FACO_ENOMEM, FACO_EDEVICE.
+ */
+int faco_build_instance(const int32_t *xy, int32_t n, const faco_params *p,
+                        void *hip_stream, faco_instance **out);
+
+/*
+ * Enqueue `iterations` more iterations of Alg. 2's main loop on the handle's
+ * stream and return without waiting.  The iteration counter persists, so two
+ * calls of a and b iterations give exactly the state of one call of a + b.
+ * Errors: FACO_EINVAL (iterations < 0 or NULL handle), FACO_EDEVICE.
+ */
+int faco_run_iterations(faco_instance *h, int32_t iterations);
+
+/*
+ * Wait for the handle's stream and copy the global-best tour (n int32 into
+ * the caller's host buffer, exactly as stored: tour_out[0] is not rotated)
+ * and its cost.  Either pointer may be NULL.
+ * Errors: FACO_EINVAL, FACO_EDEVICE.
+ */
+int faco_get_best_tour(faco_instance *h, int32_t *tour_out,
+                       int64_t *length_out);
+
+/* Free all device state of the handle.  NULL is allowed. */
+void faco_destroy_instance(faco_instance *h);
+
+/* Last error message of the handle, or of the calling thread if h is NULL.
+ * The string stays valid until the next call on the same handle/thread. */
+const char *faco_last_error(const faco_instance *h);
+
+/*
+ * Advance several instances by `iterations` each in shared launches: one
+ * kernel launch per phase covers the ants of every instance.  Each instance
+ * ends in exactly the state a solo faco_run_iterations would give it.
+ *   hs          host array of `count` handles, all distinct.
+ *   hip_stream  stream for the shared launches (NULL = default); the call
+ *               orders itself after each handle's own stream and the handles'
+ *               later calls after it.
+ * Returns after enqueue.  Errors: FACO_EINVAL, FACO_ENOMEM, FACO_EDEVICE.
+ */
+int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
+                   void *hip_stream);
+
+/* Debug / test dumps of the state after the last completed iteration.  Sync,
+ * then copy `bytes` bytes into the host buffer `out`; `bytes` must equal the
+ * size given below, otherwise FACO_EINVAL. */
+enum {
+  FACO_DBG_ANT_ROUTES = 0,   /* int32 [n_ants][n]                            */
+  FACO_DBG_ANT_LENGTHS = 1,  /* int64 [n_ants]                               */
+  FACO_DBG_PHEROMONE = 2,    /* float [n][k_eff]                             */
+  FACO_DBG_SOURCE = 3,       /* int32 [n]                                    */
+  FACO_DBG_LIMITS = 4,       /* float [3]: tau_min, tau_max, last delta      */
+  FACO_DBG_COUNTERS = 5,     /* int64 [n_ants][FACO_NCNT]                    */
+  FACO_DBG_CAND_LISTS = 6,   /* int32 [n][k_eff]                             */
+  FACO_DBG_BACKUP_LISTS = 7, /* int32 [n][bl_eff]                            */
+  FACO_DBG_HEURISTIC = 8,    /* float [n][k_eff]                             */
+  FACO_DBG_INFO = 9,         /* int64 [8]: iterations, k_eff, bl_eff, last
+                                iteration-best ant, last source was gbest,
+                                initial length, gbest length, source length  */
+  FACO_DBG_INIT_COUNTERS = 10 /* int64 [FACO_NCNT] of the initial solution   */
+};
+/* per-ant counters (same meaning as the oracle's) */
+enum {
+  FACO_CNT_ACO_STEPS = 0,
+  FACO_CNT_COPIED,
+  FACO_CNT_BACKUP,
+  FACO_CNT_FALLBACK,
+  FACO_CNT_NEW_EDGES,
+  FACO_CNT_LS_POPS,
+  FACO_CNT_MOVES_2OPT,
+  FACO_CNT_MOVES_OROPT,
+  FACO_CNT_MOVED_ELEMS,
+  FACO_CNT_SWEEPS,
+  FACO_CNT_CHECKLIST0,
+  FACO_CNT_LS_GAIN,
+  FACO_NCNT
+};
+int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t bytes);
+
+/* Device bytes the instance holds (coordinates, lists, pheromone, tours,
+ * per-ant scratch), for admission by footprint.  Pure arithmetic; valid
+ * without a GPU.  Returns 0 for invalid arguments. */
+uint64_t faco_footprint_bytes(int32_t n, const faco_params *p);
+
+/* Kernel timing.  When enabled, each phase launch of faco_run_iterations is
+ * bracketed by HIP events on the handle's stream.  faco_phase_times syncs and
+ * returns, per phase (0 = ants: construction + local search, 1 = colony
+ * update, 2 = source materialisation, 3 = pheromone update), the summed
+ * milliseconds in ms_out[phase] and the launch count in launches[phase]. */
+int faco_set_timing(faco_instance *h, int32_t enable);
+int faco_phase_times(faco_instance *h, double *ms_out /* [4] */,
+                     int64_t *launches /* [4] */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
