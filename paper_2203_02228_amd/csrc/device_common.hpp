@@ -1,0 +1,135 @@
+// device_common.hpp -- wave64 helpers, EUC_2D cost and Philox4x64-10 for the
+// FACO kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FACO_DEV __device__ __forceinline__
+
+namespace faco {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- wave ---
+
+FACO_DEV int lane_id() { return (int)__lane_id(); }
+
+FACO_DEV uint64_t ballot(bool p) { return (uint64_t)__ballot((int)p); }
+
+FACO_DEV int ctz64(uint64_t m) { return __builtin_ctzll(m); }
+FACO_DEV int msb64(uint64_t m) { return 63 - __builtin_clzll(m); }
+
+FACO_DEV int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+FACO_DEV float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+FACO_DEV int64_t readlane_i64(int64_t v, int l) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+FACO_DEV int2 readlane_i2(int2 v, int l) {
+  return make_int2(readlane_i(v.x, l), readlane_i(v.y, l));
+}
+
+FACO_DEV int64_t shfl_xor_i64(int64_t v, int m) {
+  int lo = __shfl_xor((int)(uint32_t)v, m);
+  int hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+FACO_DEV int64_t wave_max_i64(int64_t v) {
+  for (int m = 32; m >= 1; m >>= 1) {
+    int64_t o = shfl_xor_i64(v, m);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+FACO_DEV int64_t wave_min_i64(int64_t v) {
+  for (int m = 32; m >= 1; m >>= 1) {
+    int64_t o = shfl_xor_i64(v, m);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+FACO_DEV int wave_sum_i32(int v) {
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+FACO_DEV int wave_min_i32(int v) {
+  for (int m = 32; m >= 1; m >>= 1) {
+    int o = __shfl_xor(v, m);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+// Make this wave's global and LDS writes visible to its other lanes.
+FACO_DEV void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// --------------------------------------------------------------- bitmap ---
+
+FACO_DEV bool bit_get(const uint32_t *bm, int x) {
+  return (bm[x >> 5] >> (x & 31)) & 1u;
+}
+FACO_DEV void bit_set(uint32_t *bm, int x) { atomicOr(&bm[x >> 5], 1u << (x & 31)); }
+FACO_DEV void bit_clear(uint32_t *bm, int x) {
+  atomicAnd(&bm[x >> 5], ~(1u << (x & 31)));
+}
+
+// ---------------------------------------------------------------- cost ---
+// TSPLIB EUC_2D: nint(sqrt(dx^2 + dy^2)).  With |dx|,|dy| < 2^23 the squared
+// length is an exact binary64 integer and the rounded square root decides
+// nint exactly (no integer is within one ulp of a half-integer square root).
+
+FACO_DEV double sqd(int2 a, int2 b) {
+  double dx = (double)(a.x - b.x);
+  double dy = (double)(a.y - b.y);
+  return dx * dx + dy * dy;
+}
+FACO_DEV int cost(int2 a, int2 b) { return (int)floor(sqrt(sqd(a, b)) + 0.5); }
+
+// ----------------------------------------------------------- Philox4x64 ---
+// Salmon et al., SC'11: 10 rounds, multipliers M0, M1, Weyl key increments.
+
+constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
+
+enum : uint64_t { kPurposeRoulette = 0, kPurposeStart = 1, kPurposeSource = 2 };
+
+FACO_DEV uint64_t philox_word0(uint64_t key0, uint64_t c0, uint64_t c1,
+                               uint64_t c2, uint64_t c3) {
+  uint64_t k0 = key0, k1 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    uint64_t hi0 = __umul64hi(kM0, c0), lo0 = kM0 * c0;
+    uint64_t hi1 = __umul64hi(kM1, c2), lo1 = kM1 * c2;
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return c0;
+}
+
+// top 24 bits as an exact binary32 in [0, 1)
+FACO_DEV float unit24(uint64_t x) {
+  return (float)(uint32_t)(x >> 40) * 0x1p-24f;
+}
+// floor(x * n / 2^64)
+FACO_DEV int uniform_node(uint64_t x, int n) {
+  return (int)__umul64hi(x, (uint64_t)n);
+}
+
+}  // namespace faco

@@ -1,0 +1,375 @@
+// faco_api.hip -- host side of the C ABI declared in include/faco.h.
+//
+// Owns the device state of each instance, validates arguments, launches the
+// kernels of faco_kernels.hpp on the instance's stream.  No step of the
+// method runs on the host: the host only derives p_best^(1/n) once per build
+// (a parameter of the trail-limit formula, Sec. 4.5) and marshals pointers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/faco.h"
+#include "faco_kernels.hpp"
+
+using faco::DevState;
+using faco::Inst;
+
+struct TimedLaunch {
+  int phase;
+  hipEvent_t a, b;
+};
+
+struct faco_instance {
+  faco_params p{};
+  int32_t n = 0, k = 0, bl = 0;
+  hipStream_t stream = nullptr;
+  Inst dv{};
+  std::vector<void *> allocs;
+  std::string err;
+  size_t lds_ant = 0;
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  double phase_ms[4] = {0, 0, 0, 0};
+  int64_t phase_n[4] = {0, 0, 0, 0};
+};
+
+static thread_local std::string g_err;
+
+static int set_err(faco_instance *h, int code, const std::string &msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(h, expr)                                                        \
+  do {                                                                          \
+    hipError_t _e = (expr);                                                     \
+    if (_e != hipSuccess)                                                       \
+      return set_err(h, FACO_EDEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
+  } while (0)
+
+static const char *validate(const faco_params *p, int32_t n) {
+  if (!p) return "params is NULL";
+  if (n < 4) return "n must be at least 4";
+  if (n > (1 << 18)) return "n must be at most 262144";
+  if (p->cl_size < 2 || p->cl_size > faco::kMaxCl) return "cl_size must be in [2, 32]";
+  if (p->bl_size < 0 || p->bl_size > faco::kMaxBl) return "bl_size must be in [0, 64]";
+  if (p->n_ants < 1 || p->n_ants > 4096) return "n_ants must be in [1, 4096]";
+  if (p->min_new_edges < 0) return "min_new_edges must be >= 0";
+  if (!(p->rho >= 0.0f) || !(p->rho < 1.0f)) return "rho must be in [0, 1)";
+  if (p->reserved0 != 0.0f) return "reserved0 must be 0";
+  if (!(p->p_best > 0.0) || !(p->p_best < 1.0)) return "p_best must be in (0, 1)";
+  if (!(p->p_source_gbest >= 0.0) || !(p->p_source_gbest <= 1.0))
+    return "p_source_gbest must be in [0, 1]";
+  if (p->ls_flags & ~7u) return "unknown ls_flags bits";
+  if (p->oropt_max_seg < 1 || p->oropt_max_seg > faco::kMaxOrSeg)
+    return "oropt_max_seg must be in [1, 3]";
+  return nullptr;
+}
+
+static void effective_sizes(int32_t n, const faco_params *p, int32_t *k, int32_t *bl) {
+  *k = p->cl_size < n - 1 ? p->cl_size : n - 1;
+  *bl = p->bl_size < n - 1 - *k ? p->bl_size : n - 1 - *k;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
+  if (validate(p, n)) return 0;
+  int32_t k, bl;
+  effective_sizes(n, p, &k, &bl);
+  const uint64_t N = (uint64_t)n, A = (uint64_t)p->n_ants;
+  uint64_t b = 0;
+  b += align_up(8 * N);                    // xy
+  b += 3 * align_up(4 * N * (uint64_t)k);  // cl, eta, tau
+  b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
+  b += 3 * align_up(4 * N);                // source route/pos, global best
+  b += 3 * align_up(4 * N * A);            // ant routes, pos, checklist rings
+  b += align_up(8 * A) + align_up(8 * A * faco::NCNT);
+  b += align_up(sizeof(DevState));
+  return b;
+}
+
+static int dalloc(faco_instance *h, void **ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes ? bytes : 4);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return set_err(h, FACO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  h->allocs.push_back(*ptr);
+  return FACO_OK;
+}
+
+static size_t knn_lds_bytes(int K, int BL) {
+  return sizeof(int2) * faco::kKnnTile + (sizeof(double) + sizeof(int32_t)) * (size_t)(K + BL) * 64;
+}
+
+static void begin_timed(faco_instance *h, int phase, TimedLaunch &tl) {
+  tl.phase = phase;
+  (void)hipEventCreate(&tl.a);
+  (void)hipEventCreate(&tl.b);
+  (void)hipEventRecord(tl.a, h->stream);
+}
+static void end_timed(faco_instance *h, TimedLaunch &tl) {
+  (void)hipEventRecord(tl.b, h->stream);
+  h->pending.push_back(tl);
+}
+
+// enqueue the four phases of one iteration
+static int enqueue_iteration(faco_instance *h) {
+  const Inst &I = h->dv;
+  const int n = h->n;
+  const unsigned nb_src = (unsigned)((n + 255) / 256);
+  const size_t slots = (size_t)n * (size_t)h->k;
+  const unsigned nb_tau = (unsigned)((slots + 255) / 256);
+  TimedLaunch tl;
+  if (h->timing) begin_timed(h, 0, tl);
+  hipLaunchKernelGGL(faco::ant_kernel, dim3(h->p.n_ants), dim3(64), h->lds_ant, h->stream, I, 0);
+  if (h->timing) {
+    end_timed(h, tl);
+    begin_timed(h, 1, tl);
+  }
+  hipLaunchKernelGGL(faco::colony_kernel, dim3(1), dim3(64), 0, h->stream, I);
+  if (h->timing) {
+    end_timed(h, tl);
+    begin_timed(h, 2, tl);
+  }
+  hipLaunchKernelGGL(faco::source_kernel, dim3(nb_src), dim3(256), 0, h->stream, I, 0);
+  if (h->timing) {
+    end_timed(h, tl);
+    begin_timed(h, 3, tl);
+  }
+  hipLaunchKernelGGL(faco::pheromone_kernel, dim3(nb_tau), dim3(256), 0, h->stream, I, 0);
+  if (h->timing) end_timed(h, tl);
+  HIP_TRY(h, hipGetLastError());
+  return FACO_OK;
+}
+
+extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_params *p,
+                                   void *hip_stream, faco_instance **out) {
+  if (!out) return set_err(nullptr, FACO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!xy) return set_err(nullptr, FACO_EINVAL, "xy is NULL");
+  if (const char *m = validate(p, n)) return set_err(nullptr, FACO_EINVAL, m);
+  for (int64_t i = 0; i < 2 * (int64_t)n; ++i)
+    if (xy[i] < 0 || xy[i] >= (1 << 23))
+      return set_err(nullptr, FACO_EINVAL, "coordinates must be in [0, 2^23)");
+
+  faco_instance *h = new faco_instance();
+  h->p = *p;
+  h->n = n;
+  effective_sizes(n, p, &h->k, &h->bl);
+  h->stream = (hipStream_t)hip_stream;
+  const size_t N = (size_t)n, A = (size_t)p->n_ants, K = (size_t)h->k, BL = (size_t)h->bl;
+
+  Inst &I = h->dv;
+  I.n = n;
+  I.k = h->k;
+  I.bl = h->bl;
+  I.A = p->n_ants;
+  I.m = p->min_new_edges;
+  I.rho = p->rho;
+  I.ls_flags = p->ls_flags;
+  I.oropt_max = p->oropt_max_seg;
+  I.seed = p->seed;
+  I.p_gb = p->p_source_gbest;
+  I.p_root = std::pow(p->p_best, 1.0 / (double)n);
+
+  void *ptr;
+  int rc = FACO_OK;
+#define ALLOC(field, type, count)                      \
+  if ((rc = dalloc(h, &ptr, sizeof(type) * (count)))) { \
+    faco_destroy_instance(h);                          \
+    g_err = "device allocation failed";                \
+    return rc;                                         \
+  }                                                    \
+  I.field = (type *)ptr;
+  ALLOC(xy, int2, N);
+  ALLOC(cl, int32_t, N * K);
+  ALLOC(bll, int32_t, N * BL + 1);
+  ALLOC(eta, float, N * K);
+  ALLOC(tau, float, N * K);
+  ALLOC(src_route, int32_t, N);
+  ALLOC(src_pos, int32_t, N);
+  ALLOC(gb_route, int32_t, N);
+  ALLOC(routes, int32_t, N * A);
+  ALLOC(pos, int32_t, N * A);
+  ALLOC(ring, int32_t, N * A);
+  ALLOC(lens, int64_t, A);
+  ALLOC(cnt, int64_t, A * faco::NCNT);
+  ALLOC(st, DevState, 1);
+#undef ALLOC
+
+  auto fail = [&](int code) {
+    std::string m = h->err;
+    faco_destroy_instance(h);
+    g_err = m;
+    return code;
+  };
+  hipError_t e;
+#define BTRY(expr)                                                           \
+  if ((e = (expr)) != hipSuccess) {                                          \
+    h->err = std::string(#expr ": ") + hipGetErrorString(e);                 \
+    return fail(FACO_EDEVICE);                                               \
+  }
+  BTRY(hipMemsetAsync(I.st, 0, sizeof(DevState), h->stream));
+  BTRY(hipMemcpyAsync((void *)I.xy, xy, sizeof(int2) * N, hipMemcpyHostToDevice, h->stream));
+
+  const size_t klds = knn_lds_bytes(h->k, h->bl);
+  BTRY(hipFuncSetAttribute((const void *)faco::knn_kernel,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)klds));
+  hipLaunchKernelGGL(faco::knn_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), klds,
+                     h->stream, I.xy, n, h->k, h->bl, (int32_t *)I.cl, (int32_t *)I.bll,
+                     (float *)I.eta, I.st);
+  BTRY(hipGetLastError());
+  DevState hs;
+  BTRY(hipMemcpyAsync(&hs, I.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  BTRY(hipStreamSynchronize(h->stream));
+  if (hs.dup) {
+    h->err = "two cities share coordinates";
+    return fail(FACO_EDUP);
+  }
+
+  h->lds_ant = sizeof(uint32_t) * 2 * (size_t)((n + 31) / 32);
+  BTRY(hipFuncSetAttribute((const void *)faco::ant_kernel,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_ant));
+  // initial solution (ant slot 0), limits, tau = tau_max, source = global best
+  hipLaunchKernelGGL(faco::ant_kernel, dim3(1), dim3(64), h->lds_ant, h->stream, I, 1);
+  hipLaunchKernelGGL(faco::init_state_kernel, dim3(1), dim3(1), 0, h->stream, I);
+  hipLaunchKernelGGL(faco::source_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     h->stream, I, 1);
+  const size_t slots = N * K;
+  hipLaunchKernelGGL(faco::pheromone_kernel, dim3((unsigned)((slots + 255) / 256)), dim3(256),
+                     0, h->stream, I, 1);
+  BTRY(hipGetLastError());
+  BTRY(hipStreamSynchronize(h->stream));
+#undef BTRY
+  *out = h;
+  return FACO_OK;
+}
+
+extern "C" int faco_run_iterations(faco_instance *h, int32_t iterations) {
+  if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
+  if (iterations < 0) return set_err(h, FACO_EINVAL, "iterations must be >= 0");
+  for (int32_t i = 0; i < iterations; ++i) {
+    int rc = enqueue_iteration(h);
+    if (rc) return rc;
+  }
+  return FACO_OK;
+}
+
+extern "C" int faco_get_best_tour(faco_instance *h, int32_t *tour_out, int64_t *length_out) {
+  if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (tour_out)
+    HIP_TRY(h, hipMemcpy(tour_out, h->dv.gb_route, sizeof(int32_t) * (size_t)h->n,
+                         hipMemcpyDeviceToHost));
+  if (length_out) {
+    DevState hs;
+    HIP_TRY(h, hipMemcpy(&hs, h->dv.st, sizeof(DevState), hipMemcpyDeviceToHost));
+    *length_out = hs.gb_len;
+  }
+  return FACO_OK;
+}
+
+extern "C" void faco_destroy_instance(faco_instance *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto &tl : h->pending) {
+    (void)hipEventDestroy(tl.a);
+    (void)hipEventDestroy(tl.b);
+  }
+  for (void *p : h->allocs) (void)hipFree(p);
+  delete h;
+}
+
+extern "C" const char *faco_last_error(const faco_instance *h) {
+  return h ? h->err.c_str() : g_err.c_str();
+}
+
+extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t bytes) {
+  if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
+  if (!out) return set_err(h, FACO_EINVAL, "out is NULL");
+  const size_t N = (size_t)h->n, A = (size_t)h->p.n_ants, K = (size_t)h->k, BL = (size_t)h->bl;
+  const void *src = nullptr;
+  size_t need = 0;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  DevState hs;
+  HIP_TRY(h, hipMemcpy(&hs, h->dv.st, sizeof(DevState), hipMemcpyDeviceToHost));
+  switch (what) {
+    case FACO_DBG_ANT_ROUTES: src = h->dv.routes; need = 4 * N * A; break;
+    case FACO_DBG_ANT_LENGTHS: src = h->dv.lens; need = 8 * A; break;
+    case FACO_DBG_PHEROMONE: src = h->dv.tau; need = 4 * N * K; break;
+    case FACO_DBG_SOURCE: src = h->dv.src_route; need = 4 * N; break;
+    case FACO_DBG_COUNTERS: src = h->dv.cnt; need = 8 * A * faco::NCNT; break;
+    case FACO_DBG_CAND_LISTS: src = h->dv.cl; need = 4 * N * K; break;
+    case FACO_DBG_BACKUP_LISTS: src = h->dv.bll; need = 4 * N * BL; break;
+    case FACO_DBG_HEURISTIC: src = h->dv.eta; need = 4 * N * K; break;
+    case FACO_DBG_LIMITS: {
+      if (bytes != 12) return set_err(h, FACO_EINVAL, "size mismatch");
+      float f[3] = {hs.tau_min, hs.tau_max, hs.delta};
+      std::memcpy(out, f, 12);
+      return FACO_OK;
+    }
+    case FACO_DBG_INFO: {
+      if (bytes != 64) return set_err(h, FACO_EINVAL, "size mismatch");
+      int64_t v[8] = {hs.iter, h->k, h->bl, hs.ib, hs.src_gb, hs.init_len, hs.gb_len, hs.src_len};
+      std::memcpy(out, v, 64);
+      return FACO_OK;
+    }
+    case FACO_DBG_INIT_COUNTERS: {
+      if (bytes != 8 * faco::NCNT) return set_err(h, FACO_EINVAL, "size mismatch");
+      std::memcpy(out, hs.init_cnt, 8 * faco::NCNT);
+      return FACO_OK;
+    }
+    default: return set_err(h, FACO_EINVAL, "unknown dump");
+  }
+  if (bytes != need) return set_err(h, FACO_EINVAL, "size mismatch");
+  if (need) HIP_TRY(h, hipMemcpy(out, src, need, hipMemcpyDeviceToHost));
+  return FACO_OK;
+}
+
+extern "C" int faco_set_timing(faco_instance *h, int32_t enable) {
+  if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
+  h->timing = enable != 0;
+  return FACO_OK;
+}
+
+extern "C" int faco_phase_times(faco_instance *h, double *ms_out, int64_t *launches) {
+  if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (auto &tl : h->pending) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, tl.a, tl.b);
+    h->phase_ms[tl.phase] += ms;
+    h->phase_n[tl.phase] += 1;
+    (void)hipEventDestroy(tl.a);
+    (void)hipEventDestroy(tl.b);
+  }
+  h->pending.clear();
+  for (int i = 0; i < 4; ++i) {
+    if (ms_out) ms_out[i] = h->phase_ms[i];
+    if (launches) launches[i] = h->phase_n[i];
+    h->phase_ms[i] = 0;
+    h->phase_n[i] = 0;
+  }
+  return FACO_OK;
+}
+
+extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
+                              void *hip_stream) {
+  (void)hip_stream;
+  if (!hs || count < 0) return set_err(nullptr, FACO_EINVAL, "bad handle array");
+  if (iterations < 0) return set_err(nullptr, FACO_EINVAL, "iterations must be >= 0");
+  for (int32_t i = 0; i < count; ++i) {
+    int rc = faco_run_iterations(hs[i], iterations);
+    if (rc) return rc;
+  }
+  return FACO_OK;
+}

@@ -1,0 +1,70 @@
+// faco_device.hpp -- device-side instance view and per-instance state.
+#pragma once
+#include <stdint.h>
+
+namespace faco {
+
+// Scalars that change every iteration, kept on the device so that a whole
+// run of iterations is enqueued without host round trips.
+struct DevState {
+  int64_t iter;      // completed iterations
+  int64_t gb_len;    // global-best cost
+  int64_t src_len;   // cost of the current source solution
+  int64_t init_len;  // cost of the initial solution
+  float tau_min, tau_max, delta, pad0;
+  int32_t ib;        // iteration-best ant of the last iteration
+  int32_t src_gb;    // 1 if the last source choice took the global best
+  int32_t improved;  // 1 if the last iteration improved the global best
+  int32_t dup;       // set by the list kernel when two cities coincide
+  int64_t init_cnt[12];
+};
+
+// Device view of one instance (kernel argument).  Layouts:
+//   xy        int2 [n]           (x, y)
+//   cl, eta,
+//   tau       [n][k]             row-major, k = effective candidate-list length
+//   bll       [n][bl]            backup lists
+//   routes,
+//   pos, ring [A][n]             ant tours, their inverses, LS checklist rings
+//   cnt       int64 [A][12]      per-ant counters
+struct Inst {
+  int32_t n, k, bl, A, m;
+  float rho;
+  uint32_t ls_flags;
+  int32_t oropt_max;
+  uint64_t seed;
+  double p_gb;   // probability the source is the global best
+  double p_root; // p_best^(1/n)
+  const int2 *xy;
+  const int32_t *cl;
+  const int32_t *bll;
+  const float *eta;
+  float *tau;
+  int32_t *src_route, *src_pos, *gb_route;
+  int32_t *routes, *pos, *ring;
+  int64_t *lens, *cnt;
+  DevState *st;
+};
+
+enum {
+  CNT_ACO_STEPS = 0,
+  CNT_COPIED,
+  CNT_BACKUP,
+  CNT_FALLBACK,
+  CNT_NEW_EDGES,
+  CNT_LS_POPS,
+  CNT_MOVES_2OPT,
+  CNT_MOVES_OROPT,
+  CNT_MOVED_ELEMS,
+  CNT_SWEEPS,
+  CNT_CHECKLIST0,
+  CNT_LS_GAIN,
+  NCNT
+};
+
+constexpr uint32_t LS_2OPT = 1u, LS_OROPT = 2u, LS_SWEEP = 4u;
+constexpr int kMaxCl = 32;
+constexpr int kMaxBl = 64;
+constexpr int kMaxOrSeg = 3;
+
+}  // namespace faco
