@@ -1,0 +1,319 @@
+"""Benchmark of the FACO hot path on one MI355X.
+
+A step is one iteration of the FACO main loop over the whole colony: every ant
+builds its focused tour and improves it with 2-opt/Or-opt, then the colony
+update and the pheromone update run.  The default workload is the 100 000-city
+stipple-like instance (64 ants, 32 new edges, retention 0.5, k = 16,
+backup lists of 64).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_ant(cnt, n, k, bl):
+    """Bytes the array-based ant must move, from its counters (per ant-tour):
+    ACO step: candidate, pheromone and heuristic rows (12k) + source
+    position/neighbours (12) + coordinates (8) + route/pos writes (8);
+    copied city: source read (4) + coordinates (8) + route/pos writes (8);
+    backup pick: backup row (4 bl); fallback: coordinate scan (8n);
+    LS pop: candidate row (4k) + per candidate, for both 2-opt loops,
+    position, neighbour and two coordinates (2 * 24 k) + own neighbourhood (64);
+    moved element: route read + route write + pos write (12)."""
+    S, C, B, Fb = cnt[:, 0], cnt[:, 1], cnt[:, 2], cnt[:, 3]
+    P, R = cnt[:, 5], cnt[:, 8]
+    return (S * (12 * k + 28) + 20 * C + B * 4 * bl + Fb * 8 * n +
+            P * (52 * k + 64) + 12 * R).astype(np.float64)
+
+
+def cpu_baseline(xy, params, warmup, steps, budget_s=20.0):
+    """The oracle on the host over the same iterations as the timed GPU region
+    (fewer if the budget runs out first)."""
+    from oracle import oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.time()
+    o = O.Oracle(xy, threads=threads, **params)
+    build_s = time.time() - t0
+    o.run(warmup)
+    iters, t_run = 0, 0.0
+    while t_run < budget_s and iters < steps:
+        t1 = time.time()
+        o.run(1)
+        t_run += time.time() - t1
+        iters += 1
+    A = params["n_ants"]
+    o.close()
+    return {"value": A * iters / t_run, "unit": "ant-tours/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"iterations {warmup + 1}..{warmup + iters} of the same instance "
+                      f"({iters} iterations, {t_run:.1f} s; build {build_s:.1f} s untimed)"}
+
+
+def _gen_points(args):
+    from paper_2203_02228_amd import instances as I
+    kind, n, seed = args
+    return I.make_points(kind, n, seed)
+
+
+def gen_points_parallel(specs, procs=None):
+    """Generate [(kind, n, seed)] point sets in a process pool (deterministic)."""
+    import multiprocessing as mp
+    procs = procs or min(16, os.cpu_count() or 1, len(specs))
+    if procs <= 1:
+        return [_gen_points(s) for s in specs]
+    with mp.get_context("fork").Pool(procs) as pool:
+        return pool.map(_gen_points, specs)
+
+
+def run_batch_mode(args):
+    """Uneven batch (256 instances, n log-uniform in [200, 5000], k 12, 16
+    ants, m 8, 300 iterations): shared graph-replayed launches vs one
+    instance at a time, at equal iteration budgets; results must agree."""
+    import torch
+    from paper_2203_02228_amd import faco as F
+    from paper_2203_02228_amd import instances as I
+    ws = I.batch_instances(count=args.batch_count)
+    iters = args.batch_iterations or ws[0].iterations
+    pts = gen_points_parallel([(w.kind, w.n, w.instance_seed) for w in ws])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    best = {}
+    for apb in (1, 2, 4):  # autotune ants per workgroup on a short run
+        F.faco_set_batch_ants_per_block(apb)
+        hs = [F.faco_build_instance(p, stream=stream, **w.params()) for p, w in zip(pts, ws)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.faco_run_batch(hs, 10, stream=stream)
+        torch.cuda.synchronize()
+        best[apb] = time.perf_counter() - t0
+        for h in hs:
+            h.close()
+    apb = min(best, key=best.get)
+    F.faco_set_batch_ants_per_block(apb)
+    print(f"[bench] batch autotune {best} -> ants/block {apb}", file=sys.stderr, flush=True)
+    hs = [F.faco_build_instance(p, stream=stream, **w.params()) for p, w in zip(pts, ws)]
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    F.faco_run_batch(hs, iters, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_batch = ev0.elapsed_time(ev1) * 1e-3
+    res_batch = [F.faco_get_best_tour(h)[1] for h in hs]
+    for h in hs:
+        h.close()
+    # one instance per launch sequence, on a subset
+    sub = min(args.batch_seq_count, len(ws))
+    hs = [F.faco_build_instance(p, stream=stream, **w.params())
+          for p, w in zip(pts[:sub], ws[:sub])]
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for h in hs:
+        F.faco_run_iterations(h, iters)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_seq = ev0.elapsed_time(ev1) * 1e-3
+    res_seq = [F.faco_get_best_tour(h)[1] for h in hs]
+    for h in hs:
+        h.close()
+    same = res_seq == res_batch[:sub]
+    return {
+        "metric": "batched solves/s (256 uneven instances, 300 iterations each)",
+        "value": round(len(ws) / t_batch, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": iters, "warmup": 0, "ms_per_step": round(t_batch / iters * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i32+f32", "data": "synthetic",
+        "config": {"workload": "batch256", "instances": len(ws),
+                   "n_range": [min(w.n for w in ws), max(w.n for w in ws)],
+                   "ants": 16, "cl_size": 12, "min_new_edges": 8, "rho": 0.5,
+                   "ants_per_block": apb, "autotune_s": best},
+        "one_launch_per_instance": {"solves_per_s": round(sub / t_seq, 3), "instances": sub,
+                                    "speedup": round((len(ws) / t_batch) / (sub / t_seq), 2),
+                                    "identical_lengths": bool(same)},
+    }
+
+
+def run_served_mode(args, quick=False):
+    """Poisson stream of stipple solves (n log-uniform in [1000, 200000], 32
+    ants, m 16, 200 iterations) through the continuous-batching server, vs
+    the same requests solved one after another."""
+    import torch
+    import numpy as np
+    from paper_2203_02228_amd import faco as F
+    from paper_2203_02228_amd import instances as I
+    from paper_2203_02228_amd import serve as S
+    count = args.requests
+    reqs = I.served_requests(count=count, rate=args.rate)
+    pts = gen_points_parallel([(w.kind, w.n, w.instance_seed) for _, w in reqs])
+    torch.cuda.set_device(0)
+    srv = S.Server(hbm_budget_bytes=args.hbm_budget << 30, chunk=args.chunk)
+    t0 = time.perf_counter()
+    futs = []
+    for (arr, w), p in zip(reqs, pts):
+        now = time.perf_counter() - t0
+        if arr > now:
+            time.sleep(arr - now)
+        futs.append(srv.submit(len(futs), p, w.params(), w.iterations))
+    for f in futs:
+        f.result()
+    makespan = time.perf_counter() - t0
+    srv.close()
+    done = sorted(srv.completed, key=lambda r: r.rid)
+    lat = S.latency_stats(done)
+    lengths = {r.rid: r.result[1] for r in done}
+    # sequential plain solves of a sample of the same requests
+    sample = list(range(0, count, max(1, count // args.seq_sample)))[:args.seq_sample]
+    stream = torch.cuda.current_stream()
+    svc, same = [], True
+    for i in sample:
+        (_, w), p = reqs[i], pts[i]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h = F.faco_build_instance(p, stream=stream, **w.params())
+        F.faco_run_iterations(h, w.iterations)
+        _, L = F.faco_get_best_tour(h)
+        svc.append(time.perf_counter() - t1)
+        h.close()
+        same = same and (L == lengths[i])
+    seq_rate = len(sample) / sum(svc)
+    return {
+        "solves_per_s": round(count / makespan, 3),
+        "p50_latency_s": round(lat["p50_s"], 3), "p99_latency_s": round(lat["p99_s"], 3),
+        "requests": count, "arrival_rate_per_s": args.rate, "makespan_s": round(makespan, 2),
+        "sequential_solves_per_s": round(seq_rate, 3),
+        "sequential_sample": len(sample),
+        "identical_lengths": bool(same),
+        "n_range": [min(w.n for _, w in reqs), max(w.n for _, w in reqs)],
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="stipple100k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-iterations", type=int, default=0)
+    ap.add_argument("--batch-seq-count", type=int, default=32)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=4.0)
+    ap.add_argument("--chunk", type=int, default=10)
+    ap.add_argument("--hbm-budget", type=int, default=64, help="GiB for resident solves")
+    ap.add_argument("--seq-sample", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(ants shard across GPUs by design, but this build measures one GPU)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "batch256":
+        print(json.dumps(run_batch_mode(args)), flush=True)
+        return
+    if args.workload == "served":
+        out = run_served_mode(args)
+        out.update({"metric": "served solves/s (Poisson stipple requests, 200 iterations)",
+                    "value": out["solves_per_s"], "unit": "solves/s", "n_gpus": 1})
+        print(json.dumps(out), flush=True)
+        return
+
+    import torch
+    from paper_2203_02228_amd import faco as F
+    from paper_2203_02228_amd import instances as I
+
+    w = I.WORKLOADS[args.workload]
+    params = w.params()
+    xy = w.points()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    g = F.faco_build_instance(xy, stream=stream, **params)
+    build_s = time.time() - t0
+    print(f"[bench] built {w.name} n={w.n} in {build_s:.2f} s", file=sys.stderr, flush=True)
+    F.faco_run_iterations(g, args.warmup)
+    torch.cuda.synchronize()
+    F.faco_phase_times(g)  # clear
+    F.faco_set_timing(g, True)
+
+    n, k, bl, A = w.n, g.k, g.bl, w.n_ants
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tot0 = F.faco_debug_get(g, F.FACO_DBG_COUNTER_TOTALS)
+    tk0 = F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    done, chunk = 0, max(1, args.steps // 10)
+    while done < args.steps:
+        step = min(chunk, args.steps - done)
+        F.faco_run_iterations(g, step)
+        done += step
+        print(f"[bench] {done}/{args.steps} iterations enqueued", file=sys.stderr, flush=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    phase_ms, launches = F.faco_phase_times(g)
+    F.faco_set_timing(g, False)
+    tot1 = F.faco_debug_get(g, F.FACO_DBG_COUNTER_TOTALS)
+    tk = (F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS) - tk0).astype(np.float64)
+    # per ant and iteration, microseconds (100 MHz wall clock)
+    tk_us = {name: round(float(tk[:, i].mean()) / args.steps / 100.0, 1) for i, name in
+             enumerate(["construct", "ls_eval", "ls_apply", "sweep", "ant_total"])}
+    bytes_ant = float(algorithmic_bytes_per_ant(tot1 - tot0, n, k, bl).sum())
+    cnt_mean = ((tot1 - tot0).sum(0) / (A * args.steps)).tolist()
+    best_tour, best_len = F.faco_get_best_tour(g)
+    info = F.faco_debug_get(g, F.FACO_DBG_INFO)
+    g.close()
+
+    ms_per_step = total_ms / args.steps
+    ant_ms = phase_ms[0] / max(1, launches[0])
+    achieved = (bytes_ant / max(1, launches[0])) / (ant_ms * 1e-3) / 1e9
+    value = A * args.steps / (total_ms * 1e-3)
+    out = {
+        "metric": "ant-tours/s (construct+2-opt/Or-opt) at 100k cities",
+        "value": round(value, 2),
+        "unit": "ant-tours/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32+f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "ants": A, "min_new_edges": w.min_new_edges,
+                   "cl_size": k, "bl_size": bl, "rho": w.rho, "p_best": 0.05,
+                   "local_search": "2-opt+Or-opt+sweep", "iterations_timed":
+                   f"{args.warmup + 1}..{args.warmup + args.steps}",
+                   "best_length": int(best_len), "iterations_done": int(info[0])},
+        "per_ant_us": tk_us,
+        "per_ant_counters": {name: round(v, 1) for name, v in zip(F.CNT_NAMES, cnt_mean)},
+        "phase_ms_per_iteration": {name: round(phase_ms[i] / max(1, launches[i]), 4)
+                                   for i, name in enumerate(["ants", "colony", "source",
+                                                             "pheromone"])},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None, "kernel": "ant_kernel",
+                     "avg_launch_ms": round(ant_ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(xy, params, args.warmup, args.steps, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

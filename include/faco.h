@@ -69,7 +69,7 @@ typedef struct faco_instance faco_instance;
  * tau = tau_max everywhere, source = initial solution.
  *   xy         host pointer, n rows of (x, y) int32, row-major; each
  *              coordinate in [0, 2^23).  Copied; the caller keeps ownership.
- *   n          number of cities, 4 .. 2^24.
+ *   n          number of cities, 4 .. 262144 (2^18).
  *   p          parameters, copied.
  *   hip_stream hipStream_t to run on (NULL = the default stream).  The handle
  *              keeps using this stream for all later calls.
@@ -117,6 +117,11 @@ const char *faco_last_error(const faco_instance *h);
 int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
                    void *hip_stream);
 
+/* Ants (wavefronts) per workgroup in faco_run_batch launches: 1, 2 or 4
+ * (process-wide; an execution-shape choice that never changes results).
+ * Errors: FACO_EINVAL. */
+int faco_set_batch_ants_per_block(int32_t ants_per_block);
+
 /* Debug / test dumps of the state after the last completed iteration.  Sync,
  * then copy `bytes` bytes into the host buffer `out`; `bytes` must equal the
  * size given below, otherwise FACO_EINVAL. */
@@ -133,7 +138,13 @@ enum {
   FACO_DBG_INFO = 9,         /* int64 [8]: iterations, k_eff, bl_eff, last
                                 iteration-best ant, last source was gbest,
                                 initial length, gbest length, source length  */
-  FACO_DBG_INIT_COUNTERS = 10 /* int64 [FACO_NCNT] of the initial solution   */
+  FACO_DBG_INIT_COUNTERS = 10, /* int64 [FACO_NCNT] of the initial solution  */
+  FACO_DBG_COUNTER_TOTALS = 11, /* int64 [n_ants][FACO_NCNT], summed over all
+                                   iterations since the build                 */
+  FACO_DBG_PHASE_TICKS = 12 /* int64 [n_ants][8] device wall-clock ticks
+                               (100 MHz) summed since the build: [0]
+                               construction, [1] move evaluation, [2] move
+                               application, [3] sweeps, [4] whole ant        */
 };
 /* per-ant counters (same meaning as the oracle's) */
 enum {

@@ -51,6 +51,10 @@ FACO_DEV int64_t wave_min_i64(int64_t v) {
   }
   return v;
 }
+FACO_DEV int64_t wave_sum_i64(int64_t v) {
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_i64(v, m);
+  return v;
+}
 FACO_DEV int wave_sum_i32(int v) {
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
   return v;

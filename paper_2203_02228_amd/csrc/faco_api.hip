@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -87,11 +89,11 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   const uint64_t N = (uint64_t)n, A = (uint64_t)p->n_ants;
   uint64_t b = 0;
   b += align_up(8 * N);                    // xy
-  b += 3 * align_up(4 * N * (uint64_t)k);  // cl, eta, tau
+  b += 5 * align_up(4 * N * (uint64_t)k);  // cl, eta, tau, tau*eta, candidate source positions
   b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
-  b += 3 * align_up(4 * N);                // source route/pos, global best
+  b += 4 * align_up(4 * N) + align_up(8 * N); // source route/pos/edge costs, adjacency, global best
   b += 3 * align_up(4 * N * A);            // ant routes, pos, checklist rings
-  b += align_up(8 * A) + align_up(8 * A * faco::NCNT);
+  b += align_up(8 * A) + 2 * align_up(8 * A * faco::NCNT) + align_up(64 * A);
   b += align_up(sizeof(DevState));
   return b;
 }
@@ -121,6 +123,17 @@ static void end_timed(faco_instance *h, TimedLaunch &tl) {
   h->pending.push_back(tl);
 }
 
+// ant kernel specialised for the candidate-list length (KT >= k)
+typedef void (*AntKernelFn)(Inst, int);
+static AntKernelFn ant_kernel_for(int k) {
+  if (k <= 4) return faco::ant_kernel<4>;
+  if (k <= 8) return faco::ant_kernel<8>;
+  if (k <= 12) return faco::ant_kernel<12>;
+  if (k <= 16) return faco::ant_kernel<16>;
+  if (k <= 24) return faco::ant_kernel<24>;
+  return faco::ant_kernel<32>;
+}
+
 // enqueue the four phases of one iteration
 static int enqueue_iteration(faco_instance *h) {
   const Inst &I = h->dv;
@@ -130,7 +143,7 @@ static int enqueue_iteration(faco_instance *h) {
   const unsigned nb_tau = (unsigned)((slots + 255) / 256);
   TimedLaunch tl;
   if (h->timing) begin_timed(h, 0, tl);
-  hipLaunchKernelGGL(faco::ant_kernel, dim3(h->p.n_ants), dim3(64), h->lds_ant, h->stream, I, 0);
+  hipLaunchKernelGGL(ant_kernel_for(h->k), dim3(h->p.n_ants), dim3(64), h->lds_ant, h->stream, I, 0);
   if (h->timing) {
     end_timed(h, tl);
     begin_timed(h, 1, tl);
@@ -195,14 +208,20 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   ALLOC(bll, int32_t, N * BL + 1);
   ALLOC(eta, float, N * K);
   ALLOC(tau, float, N * K);
+  ALLOC(w, float, N * K);
+  ALLOC(cl_spos, int32_t, N * K);
   ALLOC(src_route, int32_t, N);
   ALLOC(src_pos, int32_t, N);
   ALLOC(gb_route, int32_t, N);
+  ALLOC(src_adj, int2, N);
+  ALLOC(src_d, int32_t, N);
   ALLOC(routes, int32_t, N * A);
   ALLOC(pos, int32_t, N * A);
   ALLOC(ring, int32_t, N * A);
   ALLOC(lens, int64_t, A);
   ALLOC(cnt, int64_t, A * faco::NCNT);
+  ALLOC(cnt_acc, int64_t, A * faco::NCNT);
+  ALLOC(ticks, int64_t, A * 8);
   ALLOC(st, DevState, 1);
 #undef ALLOC
 
@@ -219,6 +238,8 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
     return fail(FACO_EDEVICE);                                               \
   }
   BTRY(hipMemsetAsync(I.st, 0, sizeof(DevState), h->stream));
+  BTRY(hipMemsetAsync(I.cnt_acc, 0, sizeof(int64_t) * A * faco::NCNT, h->stream));
+  BTRY(hipMemsetAsync(I.ticks, 0, sizeof(int64_t) * A * 8, h->stream));
   BTRY(hipMemcpyAsync((void *)I.xy, xy, sizeof(int2) * N, hipMemcpyHostToDevice, h->stream));
 
   const size_t klds = knn_lds_bytes(h->k, h->bl);
@@ -237,10 +258,10 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   }
 
   h->lds_ant = sizeof(uint32_t) * 2 * (size_t)((n + 31) / 32);
-  BTRY(hipFuncSetAttribute((const void *)faco::ant_kernel,
+  BTRY(hipFuncSetAttribute((const void *)ant_kernel_for(h->k),
                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_ant));
   // initial solution (ant slot 0), limits, tau = tau_max, source = global best
-  hipLaunchKernelGGL(faco::ant_kernel, dim3(1), dim3(64), h->lds_ant, h->stream, I, 1);
+  hipLaunchKernelGGL(ant_kernel_for(h->k), dim3(1), dim3(64), h->lds_ant, h->stream, I, 1);
   hipLaunchKernelGGL(faco::init_state_kernel, dim3(1), dim3(1), 0, h->stream, I);
   hipLaunchKernelGGL(faco::source_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      h->stream, I, 1);
@@ -308,6 +329,8 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
     case FACO_DBG_PHEROMONE: src = h->dv.tau; need = 4 * N * K; break;
     case FACO_DBG_SOURCE: src = h->dv.src_route; need = 4 * N; break;
     case FACO_DBG_COUNTERS: src = h->dv.cnt; need = 8 * A * faco::NCNT; break;
+    case FACO_DBG_COUNTER_TOTALS: src = h->dv.cnt_acc; need = 8 * A * faco::NCNT; break;
+    case FACO_DBG_PHASE_TICKS: src = h->dv.ticks; need = 8 * A * 8; break;
     case FACO_DBG_CAND_LISTS: src = h->dv.cl; need = 4 * N * K; break;
     case FACO_DBG_BACKUP_LISTS: src = h->dv.bll; need = 4 * N * BL; break;
     case FACO_DBG_HEURISTIC: src = h->dv.eta; need = 4 * N * K; break;
@@ -362,14 +385,143 @@ extern "C" int faco_phase_times(faco_instance *h, double *ms_out, int64_t *launc
   return FACO_OK;
 }
 
+// ------------------------------------------------------------------------
+// Batched execution (faco_run_batch).  The launch tables live in a
+// process-wide workspace that grows on demand; calls are serialised.
+
+typedef void (*AntBatchFn)(const Inst *, const int2 *, int, int, int);
+static AntBatchFn ant_batch_for(int k) {
+  if (k <= 4) return faco::ant_batch_kernel<4>;
+  if (k <= 8) return faco::ant_batch_kernel<8>;
+  if (k <= 12) return faco::ant_batch_kernel<12>;
+  if (k <= 16) return faco::ant_batch_kernel<16>;
+  if (k <= 24) return faco::ant_batch_kernel<24>;
+  return faco::ant_batch_kernel<32>;
+}
+
+static std::mutex g_batch_mu;
+static int g_batch_apb = 1;  // ants (waves) per workgroup in batched launches
+struct BatchWs {
+  Inst *insts = nullptr;
+  int2 *amap = nullptr;
+  size_t cap_insts = 0, cap_amap = 0;
+  hipEvent_t last_done = nullptr;  // completion of the previous batch
+};
+// one workspace per stream, so batches on different streams run concurrently
+static std::map<hipStream_t, BatchWs> g_ws_map;
+
+extern "C" int faco_set_batch_ants_per_block(int32_t apb) {
+  if (apb != 1 && apb != 2 && apb != 4) return set_err(nullptr, FACO_EINVAL, "ants per block must be 1, 2 or 4");
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batch_apb = apb;
+  return FACO_OK;
+}
+
 extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
                               void *hip_stream) {
-  (void)hip_stream;
   if (!hs || count < 0) return set_err(nullptr, FACO_EINVAL, "bad handle array");
   if (iterations < 0) return set_err(nullptr, FACO_EINVAL, "iterations must be >= 0");
+  if (count == 0 || iterations == 0) return FACO_OK;
   for (int32_t i = 0; i < count; ++i) {
-    int rc = faco_run_iterations(hs[i], iterations);
-    if (rc) return rc;
+    if (!hs[i]) return set_err(nullptr, FACO_EINVAL, "NULL handle in batch");
+    for (int32_t j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return set_err(nullptr, FACO_EINVAL, "handles must be distinct");
   }
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  hipStream_t st = (hipStream_t)hip_stream;
+  BatchWs &g_ws = g_ws_map[st];
+  hipError_t e;
+#define BT(expr)                                                                      \
+  if ((e = (expr)) != hipSuccess)                                                     \
+    return set_err(nullptr, FACO_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e));
+  // host tables
+  std::vector<Inst> insts(count);
+  std::vector<int2> amap;
+  int kmax = 2, maxn = 0;
+  size_t lds_words = 0, max_slots = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    faco_instance *h = hs[i];
+    insts[i] = h->dv;
+    kmax = h->k > kmax ? h->k : kmax;
+    maxn = h->n > maxn ? h->n : maxn;
+    const size_t words = 2 * (size_t)((h->n + 31) / 32);
+    lds_words = words > lds_words ? words : lds_words;
+    const size_t slots = (size_t)h->n * (size_t)h->k;
+    max_slots = slots > max_slots ? slots : max_slots;
+    for (int a = 0; a < h->p.n_ants; ++a) amap.push_back(make_int2(i, a));
+  }
+  const int total = (int)amap.size();
+  const int apb = g_batch_apb;
+  const size_t lds_bytes = sizeof(uint32_t) * lds_words * (size_t)apb;
+  // the tables are shared: the previous batch must be done with them
+  if (!g_ws.last_done) BT(hipEventCreateWithFlags(&g_ws.last_done, hipEventDisableTiming));
+  const bool grow = g_ws.cap_insts < (size_t)count || g_ws.cap_amap < (size_t)total;
+  if (grow) BT(hipEventSynchronize(g_ws.last_done));
+  BT(hipStreamWaitEvent(st, g_ws.last_done, 0));
+  // device tables
+  if (g_ws.cap_insts < (size_t)count) {
+    if (g_ws.insts) (void)hipFree(g_ws.insts);
+    g_ws.insts = nullptr;
+    BT(hipMalloc((void **)&g_ws.insts, sizeof(Inst) * (size_t)count));
+    g_ws.cap_insts = (size_t)count;
+  }
+  if (g_ws.cap_amap < (size_t)total) {
+    if (g_ws.amap) (void)hipFree(g_ws.amap);
+    g_ws.amap = nullptr;
+    BT(hipMalloc((void **)&g_ws.amap, sizeof(int2) * (size_t)total));
+    g_ws.cap_amap = (size_t)total;
+  }
+  // order after the handles' own streams
+  for (int32_t i = 0; i < count; ++i) {
+    if (hs[i]->stream == st) continue;
+    hipEvent_t ev;
+    BT(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    BT(hipEventRecord(ev, hs[i]->stream));
+    BT(hipStreamWaitEvent(st, ev, 0));
+    BT(hipEventDestroy(ev));
+  }
+  BT(hipMemcpyAsync(g_ws.insts, insts.data(), sizeof(Inst) * (size_t)count,
+                    hipMemcpyHostToDevice, st));
+  BT(hipMemcpyAsync(g_ws.amap, amap.data(), sizeof(int2) * (size_t)total,
+                    hipMemcpyHostToDevice, st));
+  AntBatchFn antk = ant_batch_for(kmax);
+  BT(hipFuncSetAttribute((const void *)antk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                         (int)lds_bytes));
+  const unsigned nb_ant = (unsigned)((total + apb - 1) / apb);
+  const dim3 g_src((unsigned)((maxn + 255) / 256), (unsigned)count);
+  const dim3 g_tau((unsigned)((max_slots + 255) / 256), (unsigned)count);
+  auto enqueue = [&](hipStream_t s) {
+    hipLaunchKernelGGL(antk, dim3(nb_ant), dim3(64 * apb), lds_bytes, s, g_ws.insts, g_ws.amap,
+                       total, apb, (int)lds_words);
+    hipLaunchKernelGGL(faco::colony_batch_kernel, dim3((unsigned)count), dim3(64), 0, s,
+                       (const Inst *)g_ws.insts);
+    hipLaunchKernelGGL(faco::source_batch_kernel, g_src, dim3(256), 0, s,
+                       (const Inst *)g_ws.insts);
+    hipLaunchKernelGGL(faco::pheromone_batch_kernel, g_tau, dim3(256), 0, s,
+                       (const Inst *)g_ws.insts);
+  };
+  if (iterations == 1) {
+    enqueue(st);
+    BT(hipGetLastError());
+  } else {
+    // one iteration captured as a graph, replayed
+    hipStream_t cap;
+    BT(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    BT(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    enqueue(cap);
+    BT(hipStreamEndCapture(cap, &graph));
+    BT(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    for (int32_t it = 0; it < iterations; ++it) BT(hipGraphLaunch(exec, st));
+    BT(hipGraphExecDestroy(exec));
+    BT(hipGraphDestroy(graph));
+    BT(hipStreamDestroy(cap));
+  }
+  // later calls on each handle's stream, and the next batch, come after this one
+  BT(hipEventRecord(g_ws.last_done, st));
+  for (int32_t i = 0; i < count; ++i)
+    if (hs[i]->stream != st) BT(hipStreamWaitEvent(hs[i]->stream, g_ws.last_done, 0));
+#undef BT
   return FACO_OK;
 }

@@ -26,7 +26,8 @@ struct DevState {
 //   bll       [n][bl]            backup lists
 //   routes,
 //   pos, ring [A][n]             ant tours, their inverses, LS checklist rings
-//   cnt       int64 [A][12]      per-ant counters
+//   cnt       int64 [A][12]      per-ant counters of the last iteration
+//   cnt_acc   int64 [A][12]      the same summed over all iterations
 struct Inst {
   int32_t n, k, bl, A, m;
   float rho;
@@ -41,8 +42,13 @@ struct Inst {
   const float *eta;
   float *tau;
   int32_t *src_route, *src_pos, *gb_route;
+  int2 *src_adj;      // [n] (successor, predecessor) of each city in the source
+  float *w;           // [n][k] tau * eta of every candidate slot (this iteration)
+  int32_t *cl_spos;   // [n][k] source position of every candidate (this iteration)
+  int32_t *src_d;     // [n] cost of the source edge from position i to i + 1
   int32_t *routes, *pos, *ring;
-  int64_t *lens, *cnt;
+  int64_t *lens, *cnt, *cnt_acc;
+  int64_t *ticks;     // [A][8] wall-clock ticks per phase, summed
   DevState *st;
 };
 

@@ -18,104 +18,238 @@ FACO_DEV int wrapn(int q, int n) {
 // for 0 <= q < 2n
 FACO_DEV int wrap1(int q, int n) { return q >= n ? q - n : q; }
 
+// Offset a source position by |off| <= 256 (cheap form when n > 256).
+FACO_DEV int wrap_off(int q, int off, int n) {
+  if (n > 256) {
+    q += off;
+    return q >= n ? q - n : (q < 0 ? q + n : q);
+  }
+  return wrapn(q + off, n);
+}
+
+// Roulette draws of one ant, produced 64 steps at a time: lane j holds U for
+// step base + j (counter (t, ant, step, roulette)).
+struct DrawWindow {
+  uint64_t base;
+  float u;
+  bool valid;
+};
+
+FACO_DEV float roulette_u(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
+                          DrawWindow &W) {
+  if (!W.valid || step < W.base || step >= W.base + kWave) {
+    W.base = step;
+    W.valid = true;
+    W.u = unit24(philox_word0(I.seed, t, ant, step + (uint64_t)lane_id(), kPurposeRoulette));
+  }
+  return readlane_f(W.u, (int)(step - W.base));
+}
+
 // ===================================================================== //
 // Next-city choice (Eq. (1), then the backup list, then the nearest
-// unvisited city).  Uniform result across the wave.
+// unvisited city).  Uniform result v with its coordinates xv.
 // ===================================================================== //
 FACO_DEV int select_next(const Inst &I, int u, int2 xu, const uint32_t *vis,
                          bool greedy, uint64_t t, uint64_t ant, uint64_t step,
-                         int64_t *cnt) {
+                         DrawWindow &DW, int2 &xv, int64_t *cnt) {
   const int K = I.k, lane = lane_id();
   const size_t row = (size_t)u * (size_t)K;
-  int cand = -1;
-  bool unv = false;
-  float w = 0.0f;
-  if (lane < K) {
-    cand = I.cl[row + lane];
-    unv = !bit_get(vis, cand);
-    if (!greedy && unv) w = I.tau[row + lane] * I.eta[row + lane];
+  const bool act = lane < K;
+  // everything indexed by u is loaded at once
+  const int cand = act ? I.cl[row + lane] : 0;
+  float tv = 0.0f, ev = 0.0f;
+  if (!greedy && act) {
+    tv = I.tau[row + lane];
+    ev = I.eta[row + lane];
   }
+  const bool unv = act && !bit_get(vis, cand);
+  const int2 xc = I.xy[cand];
   const uint64_t um = ballot(unv);
   if (um) {
-    if (greedy) return readlane_i(cand, ctz64(um));
-    // cumulative sum in slot order: lane s holds fl(...fl(w_0 + w_1)... + w_s)
-    float P = 0.0f;
-    for (int j = 0; j < K; ++j) {
-      float wj = readlane_f(w, j);
-      if (j <= lane) P = P + wj;
+    int s;
+    if (greedy) {
+      s = ctz64(um);
+    } else {
+      const float w = unv ? tv * ev : 0.0f;
+      // cumulative sum in slot order: lane s holds fl(...fl(w_0 + w_1)... + w_s)
+      float P = 0.0f;
+      for (int j = 0; j < K; ++j) {
+        const float wj = readlane_f(w, j);
+        if (j <= lane) P = P + wj;
+      }
+      const float total = readlane_f(P, K - 1);
+      const float U = roulette_u(I, t, ant, step, DW);
+      const float r = U * total;
+      const uint64_t sm = ballot(act && P > r);
+      s = sm ? ctz64(sm) : msb64(um);
     }
-    const float total = readlane_f(P, K - 1);
-    const float U = unit24(philox_word0(I.seed, t, ant, step, kPurposeRoulette));
-    const float r = U * total;
-    const uint64_t sm = ballot(lane < K && P > r);
-    const int s = sm ? ctz64(sm) : msb64(um);
+    xv = readlane_i2(xc, s);
     return readlane_i(cand, s);
   }
   // backup list: first unvisited
-  int b = -1;
+  int b = 0;
   bool bu = false;
   if (lane < I.bl) {
     b = I.bll[(size_t)u * (size_t)I.bl + lane];
     bu = !bit_get(vis, b);
   }
   const uint64_t bm = ballot(bu);
+  int v;
   if (bm) {
     cnt[CNT_BACKUP]++;
-    return readlane_i(b, ctz64(bm));
-  }
-  // best heuristic value = nearest unvisited city, ties by smaller id
-  cnt[CNT_FALLBACK]++;
-  int64_t bd = INT64_MAX;
-  int bj = 0x7fffffff;
-  for (int j = lane; j < I.n; j += kWave) {
-    if (!bit_get(vis, j)) {
-      int64_t d = (int64_t)sqd(xu, I.xy[j]);
-      if (d < bd) {
-        bd = d;
-        bj = j;
+    v = readlane_i(b, ctz64(bm));
+  } else {
+    // best heuristic value = nearest unvisited city, ties by smaller id
+    cnt[CNT_FALLBACK]++;
+    int64_t bd = INT64_MAX;
+    int bj = 0x7fffffff;
+    for (int j = lane; j < I.n; j += kWave) {
+      if (!bit_get(vis, j)) {
+        const int64_t d = (int64_t)sqd(xu, I.xy[j]);
+        if (d < bd) {
+          bd = d;
+          bj = j;
+        }
       }
     }
+    const int64_t md = wave_min_i64(bd);
+    v = wave_min_i32(bd == md ? bj : 0x7fffffff);
   }
-  const int64_t md = wave_min_i64(bd);
-  return wave_min_i32(bd == md ? bj : 0x7fffffff);
+  xv = I.xy[v];
+  return v;
 }
 
 // ===================================================================== //
 // Copy-from-source: append source cities in direction `dir` starting after
-// source position pv while they are unvisited.  Returns the count.
+// source position pv while they are unvisited, 256 positions per round.
+// Edge costs come from the per-iteration source edge table.
 // ===================================================================== //
-FACO_DEV int copy_run(const Inst &I, int dir, int pv, int &k, int &u, int2 &xu,
-                      int64_t &len, int32_t *route, int32_t *pos,
-                      uint32_t *vis) {
+FACO_DEV int copy_run(const Inst &I, int dir, int pv, int &k, int &u,
+                      int64_t &len, int32_t *route, int32_t *pos, uint32_t *vis) {
   const int n = I.n, lane = lane_id();
   int app = 0, pcur = pv;
   for (;;) {
-    const int q = wrapn(pcur + dir * (lane + 1), n);
-    const int c = I.src_route[q];
-    const bool vc = bit_get(vis, c);
-    const uint64_t stop = ballot(vc);
-    const int j = stop ? ctz64(stop) : kWave;
-    const int2 xc = I.xy[c];
-    const int px = __shfl_up(xc.x, 1), py = __shfl_up(xc.y, 1);
-    const int2 xp = lane == 0 ? xu : make_int2(px, py);
-    const int d = lane < j ? cost(xp, xc) : 0;
-    if (lane < j) {
-      route[k + lane] = c;
-      pos[c] = k + lane;
-      bit_set(vis, c);
+    int c[4], d[4];
+    bool vc[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int q = wrap_off(pcur, dir * (h * kWave + lane + 1), n);
+      c[h] = I.src_route[q];
+      d[h] = I.src_d[dir > 0 ? (q == 0 ? n - 1 : q - 1) : q];
     }
-    len += wave_sum_i32(d);
-    if (j > 0) {
-      u = readlane_i(c, j - 1);
-      xu = readlane_i2(xc, j - 1);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) vc[h] = bit_get(vis, c[h]);
+    int j = 4 * kWave;
+#pragma unroll
+    for (int h = 3; h >= 0; --h) {
+      const uint64_t m = ballot(vc[h]);
+      if (m) j = h * kWave + ctz64(m);
     }
+    int64_t dsum = 0;
+    int last = 0;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int idx = h * kWave + lane;
+      if (idx < j) {
+        route[k + idx] = c[h];
+        pos[c[h]] = k + idx;
+        bit_set(vis, c[h]);
+        dsum += d[h];
+      }
+      if (idx == j - 1) last = c[h];
+    }
+    len += wave_sum_i64(dsum);
+    if (j > 0) u = readlane_i(last, (j - 1) & (kWave - 1));
     k += j;
     app += j;
     pcur = wrapn(pcur + dir * j, n);
-    wave_fence();
-    if (j < kWave) break;
+    if (j < 4 * kWave) break;
   }
   return app;
+}
+
+// ===================================================================== //
+// Speculative source-following block.  Lane i evaluates ACO step `step + i`
+// as if the ant had followed the source in direction dir for the previous i
+// steps: its current city is q_i (q_0 = u), its visited set V + {q_1..q_i}
+// (V in LDS, the q's recognised by their source positions).  The first lane
+// whose choice is not q_{i+1} ends the block; its choice is exact because
+// every earlier lane confirmed the assumption.  Same draws, same weights,
+// same order as the one-step-at-a-time rule.
+// Returns the number of steps taken; 0 means step `step` needs the backup
+// list or the nearest-city scan (no candidate unvisited).
+// ===================================================================== //
+template <int KT>
+FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
+                        int u, int dir, int k, int maxw, const uint32_t *vis, int &v,
+                        int &lastq, int64_t &src_len_sum) {
+  const int n = I.n, K = I.k, lane = lane_id();
+  const int p = I.src_pos[u];
+  const int qn = I.src_route[wrap_off(p, dir * (lane + 1), n)];  // q_{lane+1}
+  const int qu = __shfl_up(qn, 1);
+  const int ui = lane == 0 ? u : qu;                                 // q_lane
+  const int ed = I.src_d[dir > 0 ? wrap_off(p, lane, n) : wrap_off(p, -lane - 1, n)];
+  const size_t row = (size_t)ui * (size_t)K;
+  int c[KT], sp[KT];
+  float wt[KT];
+#pragma unroll
+  for (int s = 0; s < KT; ++s) {
+    if (s < K) {
+      c[s] = I.cl[row + s];
+      wt[s] = I.w[row + s];
+      sp[s] = I.cl_spos[row + s];
+    }
+  }
+  // this lane's draw
+  const float U = unit24(philox_word0(I.seed, t, ant, step + (uint64_t)lane, kPurposeRoulette));
+  float P[KT];
+  float total = 0.0f;
+  int last = -1;
+#pragma unroll
+  for (int s = 0; s < KT; ++s) {
+    if (s < K) {
+      const int off = dir > 0 ? sp[s] - p : p - sp[s];
+      const int offw = off < 0 ? off + n : off;
+      const bool visited = bit_get(vis, c[s]) || (offw >= 1 && offw <= lane);
+      if (!visited) {
+        total = total + wt[s];
+        last = s;
+      }
+      P[s] = total;
+    }
+  }
+  const bool special = last < 0;
+  int choice = 0;
+  if (!special) {
+    const float r = U * total;
+    int sel = -1;
+#pragma unroll
+    for (int s = KT - 1; s >= 0; --s)
+      if (s < K && P[s] > r) sel = s;
+    if (sel < 0) sel = last;
+#pragma unroll
+    for (int s = 0; s < KT; ++s)
+      if (s == sel) choice = c[s];
+  }
+  int valid = n - k < kWave ? n - k : kWave;  // steps left
+  valid = valid < maxw ? valid : maxw;
+  const bool match = !special && choice == qn && lane < valid;
+  const uint64_t mm = ballot(!match);
+  const int f = mm ? ctz64(mm) : kWave;
+  const int acc = f < valid ? f : valid;  // accepted source-following steps
+  src_len_sum = wave_sum_i64(lane < acc ? (int64_t)ed : 0);
+  lastq = acc > 0 ? readlane_i(qn, acc - 1) : u;
+  if (acc < valid) {
+    // lane acc decides a step off the predicted path
+    if (readlane_i(special ? 1 : 0, acc)) {
+      v = -1;
+    } else {
+      v = readlane_i(choice, acc);
+    }
+  } else {
+    v = -2;  // every step of the window followed the source
+  }
+  return acc;
 }
 
 // ===================================================================== //
@@ -123,6 +257,15 @@ FACO_DEV int copy_run(const Inst &I, int dir, int pv, int &k, int &u, int2 &xu,
 // from city 0 (initial solution), no source, no copy.
 // The checklist is written into ring[0..nchk) with its LDS bits set in inq.
 // ===================================================================== //
+FACO_DEV void append_city(int v, int k, int32_t *route, int32_t *pos, uint32_t *vis) {
+  if (lane_id() == 0) {
+    route[k] = v;
+    pos[v] = k;
+    bit_set(vis, v);
+  }
+}
+
+template <int KT>
 FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
                            int32_t *route, int32_t *pos, int32_t *ring,
                            uint32_t *vis, uint32_t *inq, int W, int &nchk,
@@ -140,53 +283,91 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
   int u = r0;
   int2 xu = I.xy[u];
   const int2 x0 = xu;
-  if (lane == 0) {
-    route[0] = u;
-    pos[u] = 0;
-    bit_set(vis, u);
-  }
-  wave_fence();
+  append_city(u, 0, route, pos, vis);
   int k = 1, new_edges = 0;
   nchk = 0;
   int64_t len = 0;
   uint64_t step = 0;
+  DrawWindow DW;
+  DW.valid = false;
+  DW.base = 0;
+  DW.u = 0.0f;
+  int dir = 1;
   while (k < n) {
-    const int v = select_next(I, u, xu, vis, greedy, t, (uint64_t)ant, step, cnt);
-    ++step;
-    const int2 xv = I.xy[v];
-    len += cost(xu, xv);
-    if (lane == 0) {
-      route[k] = v;
-      pos[v] = k;
-      bit_set(vis, v);
-    }
-    ++k;
+    int v;
+    int2 xv;
+    bool is_new = false;
     if (!greedy) {
-      const int ps = I.src_pos[u];
-      const int sn = I.src_route[ps + 1 == n ? 0 : ps + 1];
-      const int pn = I.src_route[ps == 0 ? n - 1 : ps - 1];
-      if (v != sn && v != pn) {
-        ++new_edges;
-        if (lane == 0) {
-          ring[nchk] = v;
-          bit_set(inq, v);
+      // Once new_edges >= m every ACO step is followed by a copy, so the
+      // window is one step wide.
+      const int maxw = new_edges >= I.m ? 1 : kWave;
+      int lastq;
+      int64_t srcsum;
+      const int acc = spec_block<KT>(I, t, (uint64_t)ant, step, u, dir, k, maxw, vis, v,
+                                     lastq, srcsum);
+      if (acc > 0) {
+        // accepted steps follow the source: q_1..q_acc at k..k+acc-1
+        const int p = I.src_pos[u];
+        if (lane < acc) {
+          const int q = I.src_route[wrap_off(p, dir * (lane + 1), n)];
+          route[k + lane] = q;
+          pos[q] = k + lane;
+          bit_set(vis, q);
         }
-        ++nchk;
+        k += acc;
+        step += acc;
+        len += srcsum;
+        u = lastq;
       }
+      if (v == -2) {
+        // the whole window followed the source; no step off the path
+        xu = I.xy[u];
+        v = u;
+        xv = xu;
+      } else {
+        const int2 adj = I.src_adj[u];
+        xu = I.xy[u];
+        if (v >= 0) {
+          xv = I.xy[v];
+        } else {
+          v = select_next(I, u, xu, vis, false, t, (uint64_t)ant, step, DW, xv, cnt);
+        }
+        ++step;
+        len += cost(xu, xv);
+        append_city(v, k, route, pos, vis);
+        ++k;
+        is_new = v != adj.x && v != adj.y;
+        dir = v == adj.y ? -1 : 1;
+      }
+    } else {
+      v = select_next(I, u, xu, vis, true, t, (uint64_t)ant, step, DW, xv, cnt);
+      ++step;
+      len += cost(xu, xv);
+      append_city(v, k, route, pos, vis);
+      ++k;
+    }
+    if (is_new) {
+      ++new_edges;
+      if (lane == 0) {
+        ring[nchk] = v;
+        bit_set(inq, v);
+      }
+      ++nchk;
     }
     u = v;
     xu = xv;
-    wave_fence();
     if (!greedy && new_edges >= I.m && k < n) {
       const int pv = I.src_pos[v];
-      int app = copy_run(I, +1, pv, k, u, xu, len, route, pos, vis);
-      if (app == 0) app = copy_run(I, -1, pv, k, u, xu, len, route, pos, vis);
+      int app = copy_run(I, +1, pv, k, u, len, route, pos, vis);
+      if (app == 0) app = copy_run(I, -1, pv, k, u, len, route, pos, vis);
+      if (app) xu = I.xy[u];
       cnt[CNT_COPIED] += app;
     }
   }
   len += cost(xu, x0);
   cnt[CNT_ACO_STEPS] += (int64_t)step;
   cnt[CNT_NEW_EDGES] += new_edges;
+  wave_fence();
   return len;
 }
 
@@ -196,241 +377,280 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
 struct Move {
   int kind;  // 0 none, 1 2-opt, 2 Or-opt
   int gain;
-  int w, x, y, z;
-  int f, l, p, q, a, o, b, e, L;
+  int w, x, y, z;     // 2-opt: remove (w,x), (y,z)
+  int px, py, pz;     // positions of x, y, z
+  int f, l, p, q, a, o, b, e, L;  // Or-opt
+  int fpos, pq, pp, pb, side;     // positions of f, q, p, b; e = succ(b) if side 0
+  int s0, s1, s2;     // segment in array order
 };
 
 // Or-opt variants in evaluation order, one fixed slot each:
 // slot 0..2 = forward L = 1..3, slot 3..4 = backward L = 2..3.
+// For slot (dir, L) and nb[j] = route[pa + j - 3]: lanes of f, l, p, q.
 constexpr int kOrSlots = 5;
-struct OrVariant {
-  int f, l, p, q, o, fpos, L, rem_a, g_rem;
-  int2 xo;
-  bool valid;
+FACO_DEV void or_slot_lanes(int slot, int &dir, int &L, int &lf, int &ll, int &lp, int &lq) {
+  dir = slot < 3 ? 0 : 1;
+  L = slot < 3 ? slot + 1 : slot - 1;
+  if (dir == 0) {
+    lf = 3; ll = 3 + L - 1; lp = 2; lq = 3 + L;
+  } else {
+    lf = 3 - L + 1; ll = 3; lp = 3 - L; lq = 4;
+  }
+}
+FACO_DEV int or_lmax(const Inst &I) {
+  return I.oropt_max < I.n - 3 ? I.oropt_max : I.n - 3;
+}
+
+FACO_DEV int2 shfl_i2(int2 v, int l) { return make_int2(__shfl(v.x, l), __shfl(v.y, l)); }
+
+template <int GS>
+FACO_DEV int64_t group_max(int64_t v) {
+#pragma unroll
+  for (int m = GS / 2; m >= 1; m >>= 1) {
+    const int64_t o = shfl_xor_i64(v, m);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Per-lane state of a grouped evaluation: GS lanes evaluate one city a
+// (slot s = lane % GS handles candidate s), 64 / GS cities per wave.
+struct GroupEval {
+  int a, pa, b, pb, pbs, pbp, bs, bp, nb;
+  int2 xa, xnb;
+  int64_t key2, keyo;  // group maxima: 2-opt, Or-opt (0 = none)
 };
 
-FACO_DEV void or_variants(const Inst &I, int a, int pa, int2 xa, int nb,
-                          OrVariant (&vs)[kOrSlots]) {
-  // nb on lane j holds route[pa + j - 3]
-  const int n = I.n;
-  int Lmax = I.oropt_max;
-  if (Lmax > n - 3) Lmax = n - 3;
-#pragma unroll
-  for (int slot = 0; slot < kOrSlots; ++slot) {
-    const int dir = slot < 3 ? 0 : 1;
-    const int L = slot < 3 ? slot + 1 : slot - 1;
-    OrVariant &v = vs[slot];
-    v.L = L;
-    v.valid = L <= Lmax;
-    if (dir == 0) {
-      v.f = a;
-      v.l = readlane_i(nb, 3 + L - 1);
-      v.p = readlane_i(nb, 2);
-      v.q = readlane_i(nb, 3 + L);
-      v.o = v.l;
-      v.fpos = pa;
-    } else {
-      v.l = a;
-      v.f = readlane_i(nb, 3 - L + 1);
-      v.p = readlane_i(nb, 3 - L);
-      v.q = readlane_i(nb, 4);
-      v.o = v.f;
-      v.fpos = wrapn(pa - L + 1, n);
-    }
-    const int2 xf = I.xy[v.f], xl = I.xy[v.l], xp = I.xy[v.p], xq = I.xy[v.q];
-    v.xo = dir == 0 ? xl : xf;
-    v.rem_a = dir == 0 ? cost(xp, xa) : cost(xa, xq);
-    v.g_rem = cost(xp, xf) + cost(xl, xq) - cost(xp, xq);
-  }
-}
-
-// Best move from city a, evaluated across the wave.  Ties resolve to the
-// first candidate in the sequential evaluation order of Alg. 3.
-FACO_DEV void eval_best_move(const Inst &I, uint32_t flags, int a,
-                             const int32_t *route, const int32_t *pos,
-                             Move &mv) {
+// All loads for both move kinds of every city of the wave are issued
+// together (4 dependent levels).  Keys order candidates as the sequential
+// evaluation does: 2-opt loop 1 over the list, loop 2 over the list; Or-opt
+// variants, list slots, succ before pred.
+template <int GS>
+FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
+                              const int32_t *route, const int32_t *pos) {
   const int n = I.n, K = I.k, lane = lane_id();
-  mv.kind = 0;
-  mv.gain = 0;
-  const int pa = pos[a];
-  const int nb = lane < 7 ? route[wrapn(pa + lane - 3, n)] : 0;
-  const int a_s = readlane_i(nb, 4), a_p = readlane_i(nb, 2);
-  const int2 xa = I.xy[a], xas = I.xy[a_s], xap = I.xy[a_p];
+  const int gb = lane & ~(GS - 1);
+  const int s = lane & (GS - 1);
+  const bool act = gvalid && s < K;
   const size_t row = (size_t)a * (size_t)K;
+  GroupEval R;
+  R.a = a;
+  // level 1: indexed by a
+  const int pa = pos[a];
+  const int b = act ? I.cl[row + s] : a;
+  const int2 xa = I.xy[a];
+  // level 2
+  const int nb = s < 7 ? route[wrapn(pa + s - 3, n)] : a;
+  const int pb = pos[b];
+  const int2 xb = I.xy[b];
+  // level 3
+  const int pbs = pb + 1 == n ? 0 : pb + 1, pbp = pb == 0 ? n - 1 : pb - 1;
+  const int bs = route[pbs], bp = route[pbp];
+  const int2 xnb = I.xy[nb];
+  // level 4
+  const int2 xbs = I.xy[bs], xbp = I.xy[bp];
+  R.pa = pa; R.b = b; R.pb = pb; R.pbs = pbs; R.pbp = pbp; R.bs = bs; R.bp = bp;
+  R.nb = nb; R.xa = xa; R.xnb = xnb;
+  const int2 xas = shfl_i2(xnb, gb + 4), xap = shfl_i2(xnb, gb + 2);
+  const int d_ab = cost(xa, xb);
+  R.key2 = 0;
   if (flags & LS_2OPT) {
     const int d_as = cost(xa, xas), d_ap = cost(xap, xa);
-    const int s = lane & 31;
-    const bool loop2 = lane >= 32;
-    const bool act = s < K;
-    int b = 0, other = 0, g = 0;
-    if (act) {
-      b = I.cl[row + s];
-      const int2 xb = I.xy[b];
-      const int d_ab = cost(xa, xb);
-      if (loop2 ? (d_ap > d_ab) : (d_as > d_ab)) {
-        const int pb = pos[b];
-        other = route[loop2 ? (pb == 0 ? n - 1 : pb - 1) : (pb + 1 == n ? 0 : pb + 1)];
-        const int2 xo = I.xy[other];
-        g = loop2 ? (d_ap + cost(xo, xb) - d_ab - cost(xap, xo))
-                  : (d_as + cost(xb, xo) - d_ab - cost(xas, xo));
-      }
-    }
-    const int64_t key = g > 0 ? (((int64_t)g << 8) | (int64_t)(255 - lane)) : 0;
-    const int64_t best = wave_max_i64(key);
-    if (best > 0) {
-      const int bl = 255 - (int)(best & 255);
-      const int bb = readlane_i(b, bl), oo = readlane_i(other, bl);
-      mv.kind = 1;
-      mv.gain = (int)(best >> 8);
-      if (bl < 32) {
-        mv.w = a; mv.x = a_s; mv.y = bb; mv.z = oo;
-      } else {
-        mv.w = a_p; mv.x = a; mv.y = oo; mv.z = bb;
-      }
-      return;
-    }
+    int g1 = 0, g2 = 0;
+    if (act && d_as > d_ab) g1 = d_as + cost(xb, xbs) - d_ab - cost(xas, xbs);
+    if (act && d_ap > d_ab) g2 = d_ap + cost(xbp, xb) - d_ab - cost(xap, xbp);
+    const int64_t k1 = g1 > 0 ? (((int64_t)g1 << 8) | (int64_t)(255 - s)) : 0;
+    const int64_t k2 = g2 > 0 ? (((int64_t)g2 << 8) | (int64_t)(255 - 32 - s)) : 0;
+    R.key2 = group_max<GS>(k1 > k2 ? k1 : k2);
   }
-  if (!(flags & LS_OROPT)) return;
-  OrVariant vs[kOrSlots];
-  or_variants(I, a, pa, xa, nb, vs);
-  int lbest = 0, lidx = 0;
-  int b = 0, bs = 0, bp = 0;
-  if (lane < K) {
-    b = I.cl[row + lane];
-    const int pb = pos[b];
-    const int pbs = pb + 1 == n ? 0 : pb + 1, pbp = pb == 0 ? n - 1 : pb - 1;
-    bs = route[pbs];
-    bp = route[pbp];
-    const int2 xb = I.xy[b], xbs = I.xy[bs], xbp = I.xy[bp];
-    const int d_ab = cost(xa, xb), d_bs = cost(xb, xbs), d_bp = cost(xb, xbp);
+  R.keyo = 0;
+  if (flags & LS_OROPT) {
+    const int Lmax = or_lmax(I);
+    int lbest = 0, lidx = 0;
+    const int d_bs = cost(xb, xbs), d_bp = cost(xb, xbp);
 #pragma unroll
     for (int vi = 0; vi < kOrSlots; ++vi) {
-      const OrVariant &v = vs[vi];
-      if (!v.valid) continue;
-      if (wrapn(pb - v.fpos, n) < v.L) continue;
-      if (!(d_ab < v.rem_a)) continue;
-      if (wrapn(pbs - v.fpos, n) >= v.L) {
-        const int g = v.g_rem + d_bs - d_ab - cost(v.xo, xbs);
+      int dir, L, lf, ll, lp, lq;
+      or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
+      if (L > Lmax) continue;
+      const int2 xf = shfl_i2(xnb, gb + lf), xl = shfl_i2(xnb, gb + ll);
+      const int2 xp = shfl_i2(xnb, gb + lp), xq = shfl_i2(xnb, gb + lq);
+      const int2 xo = dir == 0 ? xl : xf;
+      const int fpos = dir == 0 ? pa : wrapn(pa - L + 1, n);
+      const int rem_a = dir == 0 ? cost(xp, xa) : cost(xa, xq);
+      const int g_rem = cost(xp, xf) + cost(xl, xq) - cost(xp, xq);
+      if (!act) continue;
+      if (wrapn(pb - fpos, n) < L) continue;
+      if (!(d_ab < rem_a)) continue;
+      if (wrapn(pbs - fpos, n) >= L) {
+        const int g = g_rem + d_bs - d_ab - cost(xo, xbs);
         if (g > lbest) {
           lbest = g;
-          lidx = (vi * K + lane) * 2 + 0;
+          lidx = (vi * K + s) * 2 + 0;
         }
       }
-      if (wrapn(pbp - v.fpos, n) >= v.L) {
-        const int g = v.g_rem + d_bp - d_ab - cost(v.xo, xbp);
+      if (wrapn(pbp - fpos, n) >= L) {
+        const int g = g_rem + d_bp - d_ab - cost(xo, xbp);
         if (g > lbest) {
           lbest = g;
-          lidx = (vi * K + lane) * 2 + 1;
+          lidx = (vi * K + s) * 2 + 1;
         }
       }
     }
+    const int64_t key = lbest > 0 ? (((int64_t)lbest << 16) | (int64_t)(0xFFFF - lidx)) : 0;
+    R.keyo = group_max<GS>(key);
   }
-  const int64_t key = lbest > 0 ? (((int64_t)lbest << 16) | (int64_t)(0xFFFF - lidx)) : 0;
-  const int64_t best = wave_max_i64(key);
-  if (best > 0) {
-    const int idx = 0xFFFF - (int)(best & 0xFFFF);
-    const int side = idx & 1;
-    const int s = (idx >> 1) % K;
-    const int vi = (idx >> 1) / K;
-    OrVariant v = vs[0];
-#pragma unroll
-    for (int j = 1; j < kOrSlots; ++j)
-      if (j == vi) v = vs[j];
-    mv.kind = 2;
-    mv.gain = (int)(best >> 16);
-    mv.f = v.f; mv.l = v.l; mv.p = v.p; mv.q = v.q; mv.o = v.o; mv.L = v.L;
-    mv.a = a;
-    mv.b = readlane_i(b, s);
-    mv.e = side ? readlane_i(bp, s) : readlane_i(bs, s);
-  }
+  return R;
 }
 
-// Lane-serial test: does city x have an improving move?  (used by the sweep,
-// one city per lane)
+// The move found for the city of group j (uniform j), from the group's lanes.
+template <int GS>
+FACO_DEV Move extract_move(const Inst &I, const GroupEval &R, int j) {
+  const int n = I.n, K = I.k, base = j * GS;
+  Move mv = {};
+  const int64_t key2 = readlane_i64(R.key2, base);
+  const int a = readlane_i(R.a, base);
+  const int pa = readlane_i(R.pa, base);
+  if (key2 > 0) {
+    const int idx = 255 - (int)(key2 & 255);
+    mv.kind = 1;
+    mv.gain = (int)(key2 >> 8);
+    if (idx < 32) {  // loop 1: (a, succ a, b, succ b), flip succ a .. b
+      const int l = base + idx;
+      mv.w = a; mv.x = readlane_i(R.nb, base + 4);
+      mv.y = readlane_i(R.b, l); mv.z = readlane_i(R.bs, l);
+      mv.px = pa + 1 == n ? 0 : pa + 1;
+      mv.py = readlane_i(R.pb, l);
+      mv.pz = readlane_i(R.pbs, l);
+    } else {         // loop 2: (pred a, a, pred b, b), flip a .. pred b
+      const int l = base + idx - 32;
+      mv.w = readlane_i(R.nb, base + 2); mv.x = a;
+      mv.y = readlane_i(R.bp, l); mv.z = readlane_i(R.b, l);
+      mv.px = pa;
+      mv.py = readlane_i(R.pbp, l);
+      mv.pz = readlane_i(R.pb, l);
+    }
+    return mv;
+  }
+  const int64_t keyo = readlane_i64(R.keyo, base);
+  if (keyo <= 0) return mv;
+  const int idx = 0xFFFF - (int)(keyo & 0xFFFF);
+  const int side = idx & 1;
+  const int s = (idx >> 1) % K;
+  const int vi = (idx >> 1) / K;
+  int dir, L, lf, ll, lp, lq;
+  or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
+  const int l = base + s;
+  mv.kind = 2;
+  mv.gain = (int)(keyo >> 16);
+  mv.L = L;
+  mv.a = a;
+  mv.f = readlane_i(R.nb, base + lf);
+  mv.l = readlane_i(R.nb, base + ll);
+  mv.p = readlane_i(R.nb, base + lp);
+  mv.q = readlane_i(R.nb, base + lq);
+  mv.o = dir == 0 ? mv.l : mv.f;
+  mv.b = readlane_i(R.b, l);
+  mv.e = side ? readlane_i(R.bp, l) : readlane_i(R.bs, l);
+  mv.side = side;
+  mv.pb = readlane_i(R.pb, l);
+  mv.fpos = dir == 0 ? pa : wrapn(pa - L + 1, n);
+  mv.pq = wrapn(mv.fpos + L, n);
+  mv.pp = mv.fpos == 0 ? n - 1 : mv.fpos - 1;
+  mv.s0 = readlane_i(R.nb, base + lf);
+  mv.s1 = readlane_i(R.nb, base + lf + (L > 1 ? 1 : 0));
+  mv.s2 = readlane_i(R.nb, base + lf + (L > 2 ? 2 : 0));
+  return mv;
+}
+
+// Lane-serial test used by the sweep (one city per lane): does x have an
+// improving move?  All loads are issued before any gain is formed.
+template <int KT>
 FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
                             const int32_t *route, const int32_t *pos) {
   const int n = I.n, K = I.k;
-  const int px = pos[x];
-  const int xs = route[px + 1 == n ? 0 : px + 1];
-  const int xp = route[px == 0 ? n - 1 : px - 1];
-  const int2 cx = I.xy[x], cxs = I.xy[xs], cxp = I.xy[xp];
   const size_t row = (size_t)x * (size_t)K;
+  const int px = pos[x];
+  int b[KT];
+#pragma unroll
+  for (int s = 0; s < KT; ++s) b[s] = s < K ? I.cl[row + s] : x;
+  const int2 cx = I.xy[x];
+  int nbv[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) nbv[j] = route[wrapn(px + j - 3, n)];
+  int pb[KT];
+  int2 xb[KT];
+#pragma unroll
+  for (int s = 0; s < KT; ++s) {
+    pb[s] = pos[b[s]];
+    xb[s] = I.xy[b[s]];
+  }
+  int2 xn[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) xn[j] = I.xy[nbv[j]];
+  int bs[KT], bp[KT];
+#pragma unroll
+  for (int s = 0; s < KT; ++s) {
+    bs[s] = route[pb[s] + 1 == n ? 0 : pb[s] + 1];
+    bp[s] = route[pb[s] == 0 ? n - 1 : pb[s] - 1];
+  }
+  int2 xbs[KT], xbp[KT];
+#pragma unroll
+  for (int s = 0; s < KT; ++s) {
+    xbs[s] = I.xy[bs[s]];
+    xbp[s] = I.xy[bp[s]];
+  }
+  bool found = false;
   if (flags & LS_2OPT) {
-    const int d_s = cost(cx, cxs), d_p = cost(cxp, cx);
-    for (int s = 0; s < K; ++s) {
-      const int b = I.cl[row + s];
-      const int2 cb = I.xy[b];
-      const int d_xb = cost(cx, cb);
-      if (d_s <= d_xb && d_p <= d_xb) break;  // list sorted by distance
-      const int pb = pos[b];
-      if (d_s > d_xb) {
-        const int bs = route[pb + 1 == n ? 0 : pb + 1];
-        const int2 cbs = I.xy[bs];
-        if (d_s + cost(cb, cbs) - d_xb - cost(cxs, cbs) > 0) return true;
-      }
-      if (d_p > d_xb) {
-        const int bp = route[pb == 0 ? n - 1 : pb - 1];
-        const int2 cbp = I.xy[bp];
-        if (d_p + cost(cbp, cb) - d_xb - cost(cxp, cbp) > 0) return true;
+    const int d_s = cost(cx, xn[4]), d_p = cost(xn[2], cx);
+#pragma unroll
+    for (int s = 0; s < KT; ++s) {
+      if (s >= K) continue;
+      const int d_xb = cost(cx, xb[s]);
+      if (d_s > d_xb && d_s + cost(xb[s], xbs[s]) - d_xb - cost(xn[4], xbs[s]) > 0) found = true;
+      if (d_p > d_xb && d_p + cost(xbp[s], xb[s]) - d_xb - cost(xn[2], xbp[s]) > 0) found = true;
+    }
+  }
+  if (!found && (flags & LS_OROPT)) {
+    const int Lmax = or_lmax(I);
+#pragma unroll
+    for (int vi = 0; vi < kOrSlots; ++vi) {
+      int dir, L, lf, ll, lp, lq;
+      or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
+      if (L > Lmax) continue;
+      const int fpos = dir == 0 ? px : wrapn(px - L + 1, n);
+      const int2 xo = dir == 0 ? xn[ll] : xn[lf];
+      const int rem = dir == 0 ? cost(xn[lp], cx) : cost(cx, xn[lq]);
+      const int g_rem = cost(xn[lp], xn[lf]) + cost(xn[ll], xn[lq]) - cost(xn[lp], xn[lq]);
+#pragma unroll
+      for (int s = 0; s < KT; ++s) {
+        if (s >= K) continue;
+        const int d_xb = cost(cx, xb[s]);
+        if (!(d_xb < rem)) continue;
+        if (wrapn(pb[s] - fpos, n) < L) continue;
+        const int pbs = pb[s] + 1 == n ? 0 : pb[s] + 1, pbp = pb[s] == 0 ? n - 1 : pb[s] - 1;
+        if (wrapn(pbs - fpos, n) >= L &&
+            g_rem + cost(xb[s], xbs[s]) - d_xb - cost(xo, xbs[s]) > 0)
+          found = true;
+        if (wrapn(pbp - fpos, n) >= L &&
+            g_rem + cost(xb[s], xbp[s]) - d_xb - cost(xo, xbp[s]) > 0)
+          found = true;
       }
     }
   }
-  if (flags & LS_OROPT) {
-    int Lmax = I.oropt_max;
-    if (Lmax > n - 3) Lmax = n - 3;
-    for (int dir = 0; dir < 2; ++dir) {
-      for (int L = (dir == 0 ? 1 : 2); L <= Lmax; ++L) {
-        int f, l, p, q, fpos;
-        if (dir == 0) {
-          fpos = px;
-          f = x;
-          l = route[wrapn(px + L - 1, n)];
-          p = xp;
-          q = route[wrapn(px + L, n)];
-        } else {
-          fpos = wrapn(px - L + 1, n);
-          l = x;
-          f = route[fpos];
-          p = route[wrapn(px - L, n)];
-          q = xs;
-        }
-        const int2 cf = I.xy[f], cl_ = I.xy[l], cp = I.xy[p], cq = I.xy[q];
-        const int2 co = dir == 0 ? cl_ : cf;
-        const int rem = dir == 0 ? cost(cp, cx) : cost(cx, cq);
-        const int g_rem = cost(cp, cf) + cost(cl_, cq) - cost(cp, cq);
-        for (int s = 0; s < K; ++s) {
-          const int b = I.cl[row + s];
-          const int2 cb = I.xy[b];
-          const int d_xb = cost(cx, cb);
-          if (!(d_xb < rem)) break;  // list sorted by distance
-          const int pb = pos[b];
-          if (wrapn(pb - fpos, n) < L) continue;
-          const int pbs = pb + 1 == n ? 0 : pb + 1, pbp = pb == 0 ? n - 1 : pb - 1;
-          if (wrapn(pbs - fpos, n) >= L) {
-            const int e = route[pbs];
-            const int2 ce = I.xy[e];
-            if (g_rem + cost(cb, ce) - d_xb - cost(co, ce) > 0) return true;
-          }
-          if (wrapn(pbp - fpos, n) >= L) {
-            const int e = route[pbp];
-            const int2 ce = I.xy[e];
-            if (g_rem + cost(cb, ce) - d_xb - cost(co, ce) > 0) return true;
-          }
-        }
-      }
-    }
-  }
-  return false;
+  return found;
 }
+
+constexpr int kChunks = 8;  // 64-element chunks in flight per round
 
 // Reverse the cyclic array range of length L starting at s (wave-wide).
 FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos) {
   const int lane = lane_id();
   const int half = L >> 1;
-  for (int base = 0; base < half; base += 4 * kWave) {
-    int p1[4], p2[4], v1[4], v2[4];
+  for (int base = 0; base < half; base += kChunks * kWave) {
+    int p1[kChunks], p2[kChunks], v1[kChunks], v2[kChunks];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < kChunks; ++c) {
       const int i = base + c * kWave + lane;
       if (i < half) {
         p1[c] = wrap1(s + i, n);
@@ -440,7 +660,7 @@ FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos) {
       }
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < kChunks; ++c) {
       const int i = base + c * kWave + lane;
       if (i < half) {
         route[p1[c]] = v2[c];
@@ -450,59 +670,63 @@ FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos) {
       }
     }
   }
-  wave_fence();
 }
 
 // "Flip a section between x and y": the shorter of the paths x..y and z..w.
-FACO_DEV int apply_2opt(const Inst &I, const Move &mv, int32_t *route,
+// px, py, pz: array positions of x, y, z.
+FACO_DEV int apply_2opt(int n, int px, int py, int pz, int32_t *route,
                         int32_t *pos) {
-  const int n = I.n;
-  const int px = pos[mv.x], py = pos[mv.y];
   const int L1 = wrapn(py - px, n) + 1;
+  int moved;
   if (2 * L1 <= n) {
     reverse_range(n, px, L1, route, pos);
-    return L1;
+    moved = L1;
+  } else {
+    reverse_range(n, pz, n - L1, route, pos);
+    moved = n - L1;
   }
-  const int pz = pos[mv.z];
-  reverse_range(n, pz, n - L1, route, pos);
-  return n - L1;
+  wave_fence();
+  return moved;
 }
 
 // Or-opt: the segment and the shorter block between its old place and the
 // insertion edge exchange places (block keeps its orientation).
-FACO_DEV int apply_oropt(const Inst &I, const Move &mv, int32_t *route,
-                         int32_t *pos) {
-  const int n = I.n, L = mv.L, lane = lane_id();
-  const int pb = pos[mv.b];
-  const int sb = route[pb + 1 == n ? 0 : pb + 1];
-  int x1, x2;
-  if (sb == mv.e) {
-    x1 = mv.b;
-    x2 = mv.e;
-  } else {
-    x1 = mv.e;
-    x2 = mv.b;
+FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
+                         int pb, int fpos, int pq, int pp, int s0, int s1, int s2,
+                         int32_t *route, int32_t *pos) {
+  const int lane = lane_id();
+  int x1, px1, px2;
+  if (side == 0) {  // e = succ(b): edge (b, e)
+    x1 = b;
+    px1 = pb;
+    px2 = pb + 1 == n ? 0 : pb + 1;
+  } else {          // e = pred(b): edge (e, b)
+    x1 = e;
+    px1 = pb == 0 ? n - 1 : pb - 1;
+    px2 = pb;
   }
-  const int fpos = pos[mv.f];
-  // segment in forward order, reordered into the inserted orientation
-  const int segv = lane < L ? route[wrap1(fpos + lane, n)] : 0;
-  const bool rev = (mv.a != mv.f) != (x1 != mv.b);
-  const int src_lane = rev ? (L - 1 - lane) : lane;
-  const int ins = __shfl(segv, src_lane < 0 ? 0 : src_lane);
-  const int pq = pos[mv.q], px1 = pos[x1], pp = pos[mv.p], px2 = pos[x2];
+  // segment in array order, then in the inserted orientation
+  int segv = s0;
+  segv = lane == 1 ? s1 : segv;
+  segv = lane == 2 ? s2 : segv;
+  const bool rev = (a != f) != (x1 != b);
+  int src_lane = rev ? (L - 1 - lane) : lane;
+  src_lane = src_lane < 0 ? 0 : (src_lane > 2 ? 2 : src_lane);
+  const int ins = __shfl(segv, src_lane);
   const int D1 = wrapn(px1 - pq, n) + 1;
   const int D2 = wrapn(pp - px2, n) + 1;
+  int moved;
   if (D1 <= D2) {
     // block q..x1 moves back by L to start at fpos; segment follows it
-    for (int base = 0; base < D1; base += 4 * kWave) {
-      int v[4];
+    for (int base = 0; base < D1; base += kChunks * kWave) {
+      int v[kChunks];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < kChunks; ++c) {
         const int i = base + c * kWave + lane;
         if (i < D1) v[c] = route[wrap1(pq + i, n)];
       }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < kChunks; ++c) {
         const int i = base + c * kWave + lane;
         if (i < D1) {
           const int d = wrap1(fpos + i, n);
@@ -511,48 +735,50 @@ FACO_DEV int apply_oropt(const Inst &I, const Move &mv, int32_t *route,
         }
       }
     }
-    wave_fence();
     if (lane < L) {
       const int d = wrapn(fpos + D1 + lane, n);
       route[d] = ins;
       pos[ins] = d;
     }
-    wave_fence();
-    return D1 + L;
-  }
-  // block x2..p moves forward by L; segment goes in front of it
-  const int top = ((D2 - 1) / (4 * kWave)) * (4 * kWave);
-  for (int base = top; base >= 0; base -= 4 * kWave) {
-    int v[4];
+    moved = D1 + L;
+  } else {
+    // block x2..p moves forward by L; segment goes in front of it
+    const int top = ((D2 - 1) / (kChunks * kWave)) * (kChunks * kWave);
+    for (int base = top; base >= 0; base -= kChunks * kWave) {
+      int v[kChunks];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = base + c * kWave + lane;
-      if (i < D2) v[c] = route[wrap1(px2 + i, n)];
-    }
+      for (int c = 0; c < kChunks; ++c) {
+        const int i = base + c * kWave + lane;
+        if (i < D2) v[c] = route[wrap1(px2 + i, n)];
+      }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = base + c * kWave + lane;
-      if (i < D2) {
-        const int d = wrapn(px2 + L + i, n);
-        route[d] = v[c];
-        pos[v[c]] = d;
+      for (int c = 0; c < kChunks; ++c) {
+        const int i = base + c * kWave + lane;
+        if (i < D2) {
+          const int d = wrapn(px2 + L + i, n);
+          route[d] = v[c];
+          pos[v[c]] = d;
+        }
       }
     }
+    if (lane < L) {
+      const int d = wrap1(px2 + lane, n);
+      route[d] = ins;
+      pos[ins] = d;
+    }
+    moved = D2 + L;
   }
   wave_fence();
-  if (lane < L) {
-    const int d = wrap1(px2 + lane, n);
-    route[d] = ins;
-    pos[ins] = d;
-  }
-  wave_fence();
-  return D2 + L;
+  return moved;
 }
 
 struct Queue {
   int head, tail, count;
 };
 
+// The ring is written and read by lane 0 only (program order makes its own
+// stores visible to it); the LDS bits are read by every lane, and LDS
+// operations of one wave complete in order.
 FACO_DEV void push(int n, int x, Queue &Q, int32_t *ring, uint32_t *inq,
                    uint32_t *touched) {
   if (!bit_get(inq, x)) {
@@ -563,11 +789,11 @@ FACO_DEV void push(int n, int x, Queue &Q, int32_t *ring, uint32_t *inq,
     }
     Q.tail = Q.tail + 1 == n ? 0 : Q.tail + 1;
     Q.count++;
-    wave_fence();
   }
 }
 
 // Sweep: test every touched city (ascending id) and list the improvable ones.
+template <int KT>
 FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
                    const int32_t *route, const int32_t *pos, int32_t *ring,
                    uint32_t *inq, uint32_t *touched) {
@@ -576,7 +802,7 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
   int bx = -1, bcount = 0;
   auto flush = [&](int cnt) {
     bool f = false;
-    if (lane < cnt) f = has_improving(I, flags, bx, route, pos);
+    if (lane < cnt) f = has_improving<KT>(I, flags, bx, route, pos);
     uint64_t m = ballot(f);
     while (m) {
       const int l = ctz64(m);
@@ -608,30 +834,64 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
   return pushed;
 }
 
+FACO_DEV int64_t ticks() { return (int64_t)wall_clock64(); }
+
+template <int KT>
 FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                               int32_t *pos, int32_t *ring, uint32_t *inq,
-                              uint32_t *touched, int W, Queue Q, int64_t *cnt) {
-  const int n = I.n;
+                              uint32_t *touched, int W, Queue Q, int64_t *cnt,
+                              int64_t *tk) {
+  constexpr int GS = KT <= 16 ? 16 : 32;  // lanes per evaluated city
+  constexpr int G = kWave / GS;           // cities evaluated together
+  const int n = I.n, lane = lane_id();
+  const int grp = lane / GS;
   int64_t changes = 0, gain = 0, changes_at_sweep = -1;
-  Move mv;
   for (;;) {
     while (Q.count > 0 && changes < n) {
-      const int a = ring[Q.head];
-      Q.head = Q.head + 1 == n ? 0 : Q.head + 1;
-      Q.count--;
-      if (lane_id() == 0) bit_clear(inq, a);
-      wave_fence();
-      cnt[CNT_LS_POPS]++;
-      eval_best_move(I, flags, a, route, pos, mv);
+      // Evaluate the next G listed cities on the current tour.  The first one
+      // with a move is applied; the ones before it are popped with no move;
+      // the ones after it stay listed (their evaluation is discarded).
+      const int gcount = Q.count < G ? Q.count : G;
+      int e[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        int h = Q.head + g;
+        h = h >= n ? h - n : h;
+        e[g] = readlane_i(lane == 0 && g < gcount ? ring[h] : 0, 0);
+      }
+      int a = e[0];
+#pragma unroll
+      for (int g = 1; g < G; ++g) a = grp == g ? e[g] : a;
+      const int64_t t0 = ticks();
+      const GroupEval R = eval_group<GS>(I, flags, a, grp < gcount, route, pos);
+      const int64_t t1 = ticks();
+      tk[1] += t1 - t0;
+      const uint64_t hm = ballot((lane & (GS - 1)) == 0 && grp < gcount &&
+                                 (R.key2 > 0 || R.keyo > 0));
+      const int j = hm ? ctz64(hm) / GS : gcount;
+      const int npop = j < gcount ? j + 1 : gcount;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (g < npop) {
+          if (lane == 0) bit_clear(inq, e[g]);
+          Q.head = Q.head + 1 == n ? 0 : Q.head + 1;
+          Q.count--;
+          cnt[CNT_LS_POPS]++;
+        }
+      }
+      if (j >= gcount) continue;
+      const Move mv = extract_move<GS>(I, R, j);
       if (mv.kind == 1) {
-        cnt[CNT_MOVED_ELEMS] += apply_2opt(I, mv, route, pos);
+        cnt[CNT_MOVED_ELEMS] += apply_2opt(n, mv.px, mv.py, mv.pz, route, pos);
         push(n, mv.w, Q, ring, inq, touched);
         push(n, mv.x, Q, ring, inq, touched);
         push(n, mv.y, Q, ring, inq, touched);
         push(n, mv.z, Q, ring, inq, touched);
         cnt[CNT_MOVES_2OPT]++;
-      } else if (mv.kind == 2) {
-        cnt[CNT_MOVED_ELEMS] += apply_oropt(I, mv, route, pos);
+      } else {
+        cnt[CNT_MOVED_ELEMS] +=
+            apply_oropt(n, mv.L, mv.a, mv.f, mv.b, mv.e, mv.side, mv.pb, mv.fpos, mv.pq,
+                        mv.pp, mv.s0, mv.s1, mv.s2, route, pos);
         push(n, mv.p, Q, ring, inq, touched);
         push(n, mv.q, Q, ring, inq, touched);
         push(n, mv.b, Q, ring, inq, touched);
@@ -639,9 +899,8 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
         push(n, mv.f, Q, ring, inq, touched);
         push(n, mv.l, Q, ring, inq, touched);
         cnt[CNT_MOVES_OROPT]++;
-      } else {
-        continue;
       }
+      tk[2] += ticks() - t1;
       ++changes;
       gain += mv.gain;
     }
@@ -652,7 +911,10 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     if (changes == changes_at_sweep) break;
     changes_at_sweep = changes;
     cnt[CNT_SWEEPS]++;
-    if (sweep(I, flags, W, Q, route, pos, ring, inq, touched) == 0) break;
+    const int64_t t2 = ticks();
+    const int pushed = sweep<KT>(I, flags, W, Q, route, pos, ring, inq, touched);
+    tk[3] += ticks() - t2;
+    if (pushed == 0) break;
   }
   cnt[CNT_LS_GAIN] += gain;
   return gain;
@@ -663,6 +925,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
 // st->iter + 1.  mode 1: initial solution (nearest neighbour + LS over all
 // cities) written to the global best.
 // ===================================================================== //
+template <int KT>
 FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   const int n = I.n, lane = lane_id();
   const int W = (n + 31) >> 5;
@@ -674,14 +937,18 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   int64_t cnt[NCNT];
 #pragma unroll
   for (int c = 0; c < NCNT; ++c) cnt[c] = 0;
+  int64_t tk[4] = {0, 0, 0, 0};
   const bool init = mode == 1;
   const uint64_t t = (uint64_t)I.st->iter + 1;
   int nchk = 0;
-  int64_t len = construct(I, t, ant, init, route, pos, ring, vis, inq, W, nchk, cnt);
+  const int64_t t0 = ticks();
+  int64_t len = construct<KT>(I, t, ant, init, route, pos, ring, vis, inq, W, nchk, cnt);
+  tk[0] = ticks() - t0;
   uint32_t flags = I.ls_flags;
   Queue Q;
   if (init) {
     // the initial solution reports only its local-search counters
+#pragma unroll
     for (int c = 0; c < CNT_LS_POPS; ++c) cnt[c] = 0;
     flags = LS_2OPT | LS_SWEEP | (I.ls_flags & LS_OROPT);
     for (int i = lane; i < n; i += kWave) ring[i] = i;
@@ -706,23 +973,35 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   }
   wave_fence();
   if (flags & (LS_2OPT | LS_OROPT))
-    len -= local_search(I, flags, route, pos, ring, inq, vis, W, Q, cnt);
+    len -= local_search<KT>(I, flags, route, pos, ring, inq, vis, W, Q, cnt, tk);
   if (init) {
     for (int i = lane; i < n; i += kWave) I.gb_route[i] = route[i];
     if (lane == 0) {
       I.st->gb_len = len;
       I.st->init_len = len;
+#pragma unroll
       for (int c = 0; c < NCNT; ++c) I.st->init_cnt[c] = cnt[c];
     }
   } else if (lane == 0) {
     I.lens[ant] = len;
-    for (int c = 0; c < NCNT; ++c) I.cnt[(size_t)ant * NCNT + c] = cnt[c];
+#pragma unroll
+    for (int c = 0; c < NCNT; ++c) {
+      I.cnt[(size_t)ant * NCNT + c] = cnt[c];
+      I.cnt_acc[(size_t)ant * NCNT + c] += cnt[c];
+    }
+    int64_t *tr = I.ticks + (size_t)ant * 8;
+    tr[0] += tk[0];
+    tr[1] += tk[1];
+    tr[2] += tk[2];
+    tr[3] += tk[3];
+    tr[4] += ticks() - t0;
   }
 }
 
+template <int KT>
 __global__ void __launch_bounds__(64) ant_kernel(Inst I, int mode) {
   extern __shared__ uint32_t lds[];
-  run_ant(I, (int)blockIdx.x, mode, lds);
+  run_ant<KT>(I, (int)blockIdx.x, mode, lds);
 }
 
 // ===================================================================== //
@@ -787,17 +1066,20 @@ FACO_DEV void run_source(const Inst &I, int i, int init) {
   const int n = I.n;
   if (i >= n) return;
   const DevState *st = I.st;
-  int node;
+  const int i1 = i + 1 == n ? 0 : i + 1, i0 = i == 0 ? n - 1 : i - 1;
+  const int32_t *from;
   if (init) {
-    node = I.gb_route[i];
+    from = I.gb_route;
   } else {
     const int32_t *ibr = I.routes + (size_t)st->ib * (size_t)n;
-    const int v = ibr[i];
-    node = (st->src_gb && !st->improved) ? I.gb_route[i] : v;
-    if (st->improved) I.gb_route[i] = v;
+    from = (st->src_gb && !st->improved) ? I.gb_route : ibr;
   }
+  const int node = from[i], next = from[i1], prev = from[i0];
+  if (!init && st->improved) I.gb_route[i] = node;
   I.src_route[i] = node;
   I.src_pos[node] = i;
+  I.src_adj[node] = make_int2(next, prev);
+  I.src_d[i] = cost(I.xy[node], I.xy[next]);
 }
 
 __global__ void __launch_bounds__(256) source_kernel(Inst I, int init) {
@@ -811,20 +1093,23 @@ FACO_DEV void run_pheromone(const Inst &I, size_t idx, int init) {
   if (idx >= (size_t)n * (size_t)K) return;
   const DevState *st = I.st;
   const float tmin = st->tau_min, tmax = st->tau_max;
-  if (init) {
-    I.tau[idx] = tmax;
-    return;
-  }
-  const int i = (int)(idx / (size_t)K);
-  const int p = I.src_pos[i];
-  const int sn = I.src_route[p + 1 == n ? 0 : p + 1];
-  const int pn = I.src_route[p == 0 ? n - 1 : p - 1];
   const int j = I.cl[idx];
-  const float t1 = I.rho * I.tau[idx];
-  float t2 = (j == sn || j == pn) ? t1 + st->delta : t1;
-  if (t2 > tmax) t2 = tmax;
-  if (t2 < tmin) t2 = tmin;
-  I.tau[idx] = t2;
+  float tnew;
+  if (init) {
+    tnew = tmax;
+  } else {
+    const int i = (int)(idx / (size_t)K);
+    const int2 adj = I.src_adj[i];
+    const float t1 = I.rho * I.tau[idx];
+    float t2 = (j == adj.x || j == adj.y) ? t1 + st->delta : t1;
+    if (t2 > tmax) t2 = tmax;
+    if (t2 < tmin) t2 = tmin;
+    tnew = t2;
+  }
+  I.tau[idx] = tnew;
+  // tables read by the next construction: Eq. (1) weight and source position
+  I.w[idx] = tnew * I.eta[idx];
+  I.cl_spos[idx] = I.src_pos[j];
 }
 
 __global__ void __launch_bounds__(256) pheromone_kernel(Inst I, int init) {
@@ -845,6 +1130,37 @@ __global__ void init_state_kernel(Inst I) {
   st->src_gb = 0;
   st->improved = 0;
   st->iter = 0;
+}
+
+// ===================================================================== //
+// Batched execution: one launch per phase covers every ant of every instance
+// of a batch.  Each instance reads only its own Inst, so it evolves exactly as
+// it would alone.
+//   insts  Inst [count]
+//   amap   int2 [total ants]: (instance, ant) of wave w = block * apb + wave
+// ===================================================================== //
+template <int KT>
+__global__ void __launch_bounds__(256) ant_batch_kernel(const Inst *insts, const int2 *amap,
+                                                       int total, int apb, int lds_words) {
+  extern __shared__ uint32_t lds[];
+  const int wave = (int)(threadIdx.x / kWave);
+  const int w = (int)blockIdx.x * apb + wave;
+  if (w >= total) return;
+  const int2 m = amap[w];
+  run_ant<KT>(insts[m.x], m.y, 0, lds + (size_t)wave * (size_t)lds_words);
+}
+
+__global__ void __launch_bounds__(64) colony_batch_kernel(const Inst *insts) {
+  run_colony(insts[blockIdx.x]);
+}
+
+// blockIdx.y = instance; blocks past an instance's size return
+__global__ void __launch_bounds__(256) source_batch_kernel(const Inst *insts) {
+  run_source(insts[blockIdx.y], (int)(blockIdx.x * blockDim.x + threadIdx.x), 0);
+}
+
+__global__ void __launch_bounds__(256) pheromone_batch_kernel(const Inst *insts) {
+  run_pheromone(insts[blockIdx.y], (size_t)blockIdx.x * blockDim.x + threadIdx.x, 0);
 }
 
 // ===================================================================== //

@@ -64,7 +64,9 @@ def gaussian_mixture(n, seed, components=64, sigma_lo=5e3, sigma_hi=4e4):
 
 
 def stipple_density(rng, grid=4096, blobs=200, bands=8):
-    """Density on a grid x grid lattice: Gaussian blobs + ridge bands."""
+    """Density on a grid x grid lattice: Gaussian blobs + ridge bands.
+    Both terms are separable in x and y, so each is built from outer
+    products of 1-D profiles (cos(a + b) = cos a cos b - sin a sin b)."""
     dens = np.zeros((grid, grid), dtype=np.float32)
     ax = np.arange(grid, dtype=np.float32)
     for _ in range(blobs):
@@ -75,16 +77,27 @@ def stipple_density(rng, grid=4096, blobs=200, bands=8):
         x0, x1 = max(0, int(cx) - r), min(grid, int(cx) + r + 1)
         y0, y1 = max(0, int(cy) - r), min(grid, int(cy) + r + 1)
         gx = np.exp(-((ax[x0:x1] - cx) ** 2) / (2 * sig * sig)).astype(np.float32)
-        gy = np.exp(-((ax[y0:y1] - cy) ** 2) / (2 * sig * sig)).astype(np.float32)
-        dens[y0:y1, x0:x1] += amp * np.outer(gy, gx)
-    yy, xx = np.meshgrid(ax, ax, indexing="ij")
+        gy = (amp * np.exp(-((ax[y0:y1] - cy) ** 2) / (2 * sig * sig))).astype(np.float32)
+        dens[y0:y1, x0:x1] += np.outer(gy, gx)
+    band = np.empty((grid, grid), dtype=np.float32)
+    tmp = np.empty((grid, grid), dtype=np.float32)
+    axd = np.arange(grid, dtype=np.float64)
     for _ in range(bands):
         lam = rng.uniform(256, 2048)
         th = rng.uniform(0, math.pi)
         amp = rng.uniform(0.2, 0.6)
         ph = rng.uniform(0, 2 * math.pi)
-        arg = (2 * math.pi / lam) * (xx * math.cos(th) + yy * math.sin(th)) + ph
-        dens += (amp * np.maximum(0.0, np.cos(arg)) ** 8).astype(np.float32)
+        a = (2 * math.pi / lam) * axd * math.cos(th) + ph      # x part
+        b = (2 * math.pi / lam) * axd * math.sin(th)           # y part
+        np.multiply.outer(np.cos(b).astype(np.float32), np.cos(a).astype(np.float32), out=band)
+        np.multiply.outer(np.sin(b).astype(np.float32), np.sin(a).astype(np.float32), out=tmp)
+        band -= tmp
+        np.maximum(band, 0.0, out=band)
+        band *= band
+        band *= band
+        band *= band
+        band *= np.float32(amp)
+        dens += band
     return dens
 
 

@@ -1,0 +1,193 @@
+"""Continuous-batching solve server over the C ABI.
+
+Requests (points + parameters + an iteration budget) arrive at any time.  A
+request is admitted when its device footprint (faco_footprint_bytes: points,
+candidate/backup lists, pheromone, tours) fits in the HBM budget next to the
+solves already resident; it is then built on a builder stream and joins the
+running batch of its size class at the next batch call.  Each size class has a
+worker with its own stream that advances all of its resident solves together
+(faco_run_batch, one launch per phase) in chunks of iterations, retires the
+ones that reached their budget and admits newly built ones between chunks.
+State stays on the device from build to retirement.  The method's arithmetic
+is unchanged: a solve returns exactly what a lone faco_run_iterations run of
+the same request returns.
+"""
+import collections
+import concurrent.futures as cf
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import faco as F
+
+# upper bounds (exclusive) of the size classes, each with its own worker
+DEFAULT_CLASSES = (8_000, 40_000, 1 << 30)
+
+
+@dataclass
+class Request:
+    rid: int
+    xy: np.ndarray
+    params: dict
+    iterations: int
+    arrival: float = 0.0          # host clock when submitted
+    admitted: float = 0.0
+    built: float = 0.0
+    finished: float = 0.0
+    footprint: int = 0
+    handle: object = None
+    done_iters: int = 0
+    result: tuple = None
+    future: cf.Future = field(default_factory=cf.Future)
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes=8 << 30, chunk=10, classes=DEFAULT_CLASSES,
+                 builders=2, ants_per_block=1):
+        import torch  # streams
+        self._torch = torch
+        self.budget = int(hbm_budget_bytes)
+        self.chunk = int(chunk)
+        self.classes = tuple(classes)
+        self.used = 0
+        self.lock = threading.Condition()
+        self.waiting = collections.deque()     # not yet admitted
+        self.ready = [collections.deque() for _ in self.classes]  # built, not yet batched
+        self.closed = False
+        self.completed = []
+        self.errors = []
+        F.faco_set_batch_ants_per_block(ants_per_block)
+        self.build_streams = [torch.cuda.Stream() for _ in range(builders)]
+        self.run_streams = [torch.cuda.Stream() for _ in self.classes]
+        self.build_q = collections.deque()
+        self.threads = []
+        for b in range(builders):
+            t = threading.Thread(target=self._builder, args=(b,), daemon=True)
+            t.start()
+            self.threads.append(t)
+        for c in range(len(self.classes)):
+            t = threading.Thread(target=self._worker, args=(c,), daemon=True)
+            t.start()
+            self.threads.append(t)
+
+    # ------------------------------------------------------------- public
+    def submit(self, rid, xy, params, iterations):
+        p = F.make_params(**params)
+        fp = F.faco_footprint_bytes(len(xy), p)
+        if fp == 0:
+            raise F.FacoError(F.FACO_EINVAL, "invalid request")
+        r = Request(rid, np.ascontiguousarray(xy, np.int32), dict(params), int(iterations),
+                    arrival=time.perf_counter(), footprint=fp)
+        with self.lock:
+            if fp > self.budget:
+                r.future.set_exception(F.FacoError(F.FACO_ENOMEM,
+                                                   "request can never fit the HBM budget"))
+                return r.future
+            self.waiting.append(r)
+            self._admit_locked()
+            self.lock.notify_all()
+        return r.future
+
+    def close(self, wait=True):
+        with self.lock:
+            self.closed = True
+            self.lock.notify_all()
+        if wait:
+            for t in self.threads:
+                t.join()
+
+    def drain(self):
+        """Block until every submitted request has finished."""
+        with self.lock:
+            while self.waiting or self.build_q or any(self.ready) or self._busy():
+                self.lock.wait(0.05)
+
+    # ------------------------------------------------------------ internals
+    def _busy(self):
+        return self.used > 0
+
+    def _class_of(self, n):
+        for c, hi in enumerate(self.classes):
+            if n < hi:
+                return c
+        return len(self.classes) - 1
+
+    def _admit_locked(self):
+        # FIFO admission by footprint
+        while self.waiting and self.used + self.waiting[0].footprint <= self.budget:
+            r = self.waiting.popleft()
+            self.used += r.footprint
+            r.admitted = time.perf_counter()
+            self.build_q.append(r)
+        self.lock.notify_all()
+
+    def _release(self, r):
+        with self.lock:
+            self.used -= r.footprint
+            self._admit_locked()
+
+    def _builder(self, b):
+        stream = self.build_streams[b]
+        while True:
+            with self.lock:
+                while not self.build_q and not self.closed:
+                    self.lock.wait()
+                if not self.build_q and self.closed:
+                    return
+                r = self.build_q.popleft()
+            try:
+                r.handle = F.faco_build_instance(r.xy, stream=stream, **r.params)
+                r.built = time.perf_counter()
+                with self.lock:
+                    self.ready[self._class_of(len(r.xy))].append(r)
+                    self.lock.notify_all()
+            except Exception as e:  # report and free the slot
+                r.future.set_exception(e)
+                self.errors.append((r.rid, repr(e)))
+                self._release(r)
+
+    def _worker(self, c):
+        stream = self.run_streams[c]
+        active = []
+        while True:
+            with self.lock:
+                while not active and not self.ready[c] and not self.closed:
+                    self.lock.wait()
+                if not active and not self.ready[c] and self.closed:
+                    return
+                while self.ready[c]:
+                    active.append(self.ready[c].popleft())
+            steps = min(self.chunk, min(r.iterations - r.done_iters for r in active))
+            try:
+                F.faco_run_batch([r.handle for r in active], steps, stream=stream)
+                stream.synchronize()
+            except Exception as e:
+                for r in active:
+                    r.future.set_exception(e)
+                    self._release(r)
+                self.errors.append(("batch", repr(e)))
+                active = []
+                continue
+            keep = []
+            for r in active:
+                r.done_iters += steps
+                if r.done_iters >= r.iterations:
+                    tour, length = F.faco_get_best_tour(r.handle)
+                    r.finished = time.perf_counter()
+                    r.result = (tour, length)
+                    r.handle.close()
+                    r.handle = None
+                    self.completed.append(r)
+                    r.future.set_result((tour, length))
+                    self._release(r)
+                else:
+                    keep.append(r)
+            active = keep
+
+
+def latency_stats(reqs):
+    lat = np.array([r.finished - r.arrival for r in reqs])
+    return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "max_s": float(lat.max())}

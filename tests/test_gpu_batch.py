@@ -1,0 +1,85 @@
+"""Batched execution (faco_run_batch): every instance of an uneven batch ends
+exactly where a solo run leaves it, whatever the ants-per-workgroup shape."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2203_02228_amd import faco as F
+from paper_2203_02228_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _state(g):
+    return (F.faco_debug_get(g, F.FACO_DBG_ANT_ROUTES),
+            F.faco_debug_get(g, F.FACO_DBG_ANT_LENGTHS),
+            F.faco_debug_get(g, F.FACO_DBG_PHEROMONE),
+            F.faco_debug_get(g, F.FACO_DBG_SOURCE),
+            F.faco_debug_get(g, F.FACO_DBG_INFO),
+            F.faco_get_best_tour(g)[0])
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def _batch_workloads(count):
+    ws = I.batch_instances(count=count, n_hi=2500)
+    # mixed candidate-list lengths and ant counts exercise the shared launch
+    ws[1].cl_size = 16
+    ws[2].n_ants = 5
+    return ws
+
+
+@pytest.mark.parametrize("apb", [1, 2, 4])
+def test_batch_equals_solo(apb):
+    ws = _batch_workloads(10)
+    say(f"[gpu] batch apb={apb} sizes={[w.n for w in ws]}")
+    F.faco_set_batch_ants_per_block(apb)
+    batch = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    solo = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    F.faco_run_batch(batch, 1)      # direct launches
+    F.faco_run_batch(batch, 4)      # one captured iteration replayed 4 times
+    for g in solo:
+        F.faco_run_iterations(g, 5)
+    for w, gb, gs in zip(ws, batch, solo):
+        assert _same(_state(gb), _state(gs)), w.name
+    F.faco_set_batch_ants_per_block(1)
+    for g in batch + solo:
+        g.close()
+
+
+def test_batch_matches_oracle():
+    ws = _batch_workloads(6)
+    say(f"[gpu] batch vs oracle sizes={[w.n for w in ws]}")
+    batch = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    F.faco_run_batch(batch, 6)
+    for w, g in zip(ws[:3], batch[:3]):
+        o = O.Oracle(w.points(), threads=8, **w.params())
+        o.run(6)
+        assert np.array_equal(F.faco_debug_get(g, F.FACO_DBG_ANT_ROUTES), o.ant_routes()), w.name
+        assert np.array_equal(F.faco_debug_get(g, F.FACO_DBG_PHEROMONE), o.pheromone()), w.name
+        t, L = F.faco_get_best_tour(g)
+        ot, ol = o.best()
+        assert L == ol and np.array_equal(t, ot)
+    for g in batch:
+        g.close()
+
+
+def test_batch_rejects_bad_input():
+    w = I.WORKLOADS["uniform1k"]
+    g = F.faco_build_instance(w.points()[:300], n_ants=4)
+    with pytest.raises(F.FacoError):
+        F.faco_run_batch([g, g], 1)
+    with pytest.raises(F.FacoError):
+        F.faco_run_batch([g], -1)
+    with pytest.raises(F.FacoError):
+        F.faco_set_batch_ants_per_block(3)
+    g.close()

@@ -1,0 +1,63 @@
+"""Served stream: requests of different sizes admitted by footprint, batched
+with each other while resident; each result equals the same request solved
+alone."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2203_02228_amd import faco as F
+from paper_2203_02228_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_mix_equals_alone_under_small_budget():
+    import torch
+    from paper_2203_02228_amd import serve as S
+    torch.cuda.set_device(0)
+    sizes = [1200, 300, 5000, 800, 15000, 2500, 600, 9000]
+    reqs = []
+    for i, n in enumerate(sizes):
+        kind = "stipple" if i % 2 == 0 else "uniform"
+        xy = I.make_points(kind, n, 900 + i)
+        params = dict(n_ants=8 + (i % 3) * 4, min_new_edges=8, rho=0.5, seed=i + 1,
+                      cl_size=16 if i % 4 else 12)
+        reqs.append((xy, params, 20 + 7 * (i % 3)))
+    fps = [F.faco_footprint_bytes(len(x), F.make_params(**p)) for x, p, _ in reqs]
+    budget = max(fps) + sorted(fps)[len(fps) // 2]
+    say(f"[gpu] serve mix sizes={sizes} budget={budget}")
+    srv = S.Server(hbm_budget_bytes=budget, chunk=5, builders=2)
+    peak = [0]
+    futs = []
+    for i, (xy, p, it) in enumerate(reqs):
+        futs.append(srv.submit(i, xy, p, it))
+        time.sleep(0.01)
+        peak[0] = max(peak[0], srv.used)
+    got = [f.result(timeout=300) for f in futs]
+    srv.close()
+    assert peak[0] <= budget
+    assert srv.used == 0 and not srv.errors
+    for (xy, p, it), (tour, L) in zip(reqs, got):
+        g = F.faco_build_instance(xy, **p)
+        F.faco_run_iterations(g, it)
+        t2, L2 = F.faco_get_best_tour(g)
+        g.close()
+        assert L == L2 and np.array_equal(tour, t2)
+
+
+def test_request_larger_than_budget_is_rejected():
+    import torch
+    from paper_2203_02228_amd import serve as S
+    torch.cuda.set_device(0)
+    srv = S.Server(hbm_budget_bytes=1 << 20, chunk=5, builders=1)
+    fut = srv.submit(0, I.uniform(5000, 3), dict(n_ants=8), 10)
+    with pytest.raises(F.FacoError):
+        fut.result(timeout=60)
+    srv.close()
