@@ -214,6 +214,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB for resident solves")
     ap.add_argument("--seq-sample", type=int, default=16)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied once by a plain device-to-device copy kernel before "
+                         "the workload (scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -239,6 +242,16 @@ def main():
     params = w.params()
     xy = w.points()
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {nbytes} bytes read, {nbytes} written",
+              file=sys.stderr, flush=True)
+        del src, dst
     stream = torch.cuda.current_stream()
     t0 = time.time()
     g = F.faco_build_instance(xy, stream=stream, **params)

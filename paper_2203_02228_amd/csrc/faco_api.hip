@@ -89,7 +89,7 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   const uint64_t N = (uint64_t)n, A = (uint64_t)p->n_ants;
   uint64_t b = 0;
   b += align_up(8 * N);                    // xy
-  b += 5 * align_up(4 * N * (uint64_t)k);  // cl, eta, tau, tau*eta, candidate source positions
+  b += 6 * align_up(4 * N * (uint64_t)k);  // cl, cost, eta, tau, tau*eta, candidate source positions
   b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
   b += 4 * align_up(4 * N) + align_up(8 * N); // source route/pos/edge costs, adjacency, global best
   b += 3 * align_up(4 * N * A);            // ant routes, pos, checklist rings
@@ -207,6 +207,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   ALLOC(cl, int32_t, N * K);
   ALLOC(bll, int32_t, N * BL + 1);
   ALLOC(eta, float, N * K);
+  ALLOC(cl_d, int32_t, N * K);
   ALLOC(tau, float, N * K);
   ALLOC(w, float, N * K);
   ALLOC(cl_spos, int32_t, N * K);
@@ -247,7 +248,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)klds));
   hipLaunchKernelGGL(faco::knn_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), klds,
                      h->stream, I.xy, n, h->k, h->bl, (int32_t *)I.cl, (int32_t *)I.bll,
-                     (float *)I.eta, I.st);
+                     (float *)I.eta, (int32_t *)I.cl_d, I.st);
   BTRY(hipGetLastError());
   DevState hs;
   BTRY(hipMemcpyAsync(&hs, I.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));

@@ -40,6 +40,7 @@ struct Inst {
   const int32_t *cl;
   const int32_t *bll;
   const float *eta;
+  const int32_t *cl_d;  // [n][k] cost of every candidate slot
   float *tau;
   int32_t *src_route, *src_pos, *gb_route;
   int2 *src_adj;      // [n] (successor, predecessor) of each city in the source

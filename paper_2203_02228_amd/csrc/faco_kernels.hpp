@@ -27,66 +27,12 @@ FACO_DEV int wrap_off(int q, int off, int n) {
   return wrapn(q + off, n);
 }
 
-// Roulette draws of one ant, produced 64 steps at a time: lane j holds U for
-// step base + j (counter (t, ant, step, roulette)).
-struct DrawWindow {
-  uint64_t base;
-  float u;
-  bool valid;
-};
-
-FACO_DEV float roulette_u(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
-                          DrawWindow &W) {
-  if (!W.valid || step < W.base || step >= W.base + kWave) {
-    W.base = step;
-    W.valid = true;
-    W.u = unit24(philox_word0(I.seed, t, ant, step + (uint64_t)lane_id(), kPurposeRoulette));
-  }
-  return readlane_f(W.u, (int)(step - W.base));
-}
-
 // ===================================================================== //
-// Next-city choice (Eq. (1), then the backup list, then the nearest
-// unvisited city).  Uniform result v with its coordinates xv.
+// Backup list, then the nearest unvisited city (when no candidate of u is
+// unvisited).  Uniform result.
 // ===================================================================== //
-FACO_DEV int select_next(const Inst &I, int u, int2 xu, const uint32_t *vis,
-                         bool greedy, uint64_t t, uint64_t ant, uint64_t step,
-                         DrawWindow &DW, int2 &xv, int64_t *cnt) {
-  const int K = I.k, lane = lane_id();
-  const size_t row = (size_t)u * (size_t)K;
-  const bool act = lane < K;
-  // everything indexed by u is loaded at once
-  const int cand = act ? I.cl[row + lane] : 0;
-  float tv = 0.0f, ev = 0.0f;
-  if (!greedy && act) {
-    tv = I.tau[row + lane];
-    ev = I.eta[row + lane];
-  }
-  const bool unv = act && !bit_get(vis, cand);
-  const int2 xc = I.xy[cand];
-  const uint64_t um = ballot(unv);
-  if (um) {
-    int s;
-    if (greedy) {
-      s = ctz64(um);
-    } else {
-      const float w = unv ? tv * ev : 0.0f;
-      // cumulative sum in slot order: lane s holds fl(...fl(w_0 + w_1)... + w_s)
-      float P = 0.0f;
-      for (int j = 0; j < K; ++j) {
-        const float wj = readlane_f(w, j);
-        if (j <= lane) P = P + wj;
-      }
-      const float total = readlane_f(P, K - 1);
-      const float U = roulette_u(I, t, ant, step, DW);
-      const float r = U * total;
-      const uint64_t sm = ballot(act && P > r);
-      s = sm ? ctz64(sm) : msb64(um);
-    }
-    xv = readlane_i2(xc, s);
-    return readlane_i(cand, s);
-  }
-  // backup list: first unvisited
+FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, int64_t *cnt) {
+  const int lane = lane_id();
   int b = 0;
   bool bu = false;
   if (lane < I.bl) {
@@ -94,103 +40,149 @@ FACO_DEV int select_next(const Inst &I, int u, int2 xu, const uint32_t *vis,
     bu = !bit_get(vis, b);
   }
   const uint64_t bm = ballot(bu);
-  int v;
   if (bm) {
     cnt[CNT_BACKUP]++;
-    v = readlane_i(b, ctz64(bm));
-  } else {
-    // best heuristic value = nearest unvisited city, ties by smaller id
-    cnt[CNT_FALLBACK]++;
-    int64_t bd = INT64_MAX;
-    int bj = 0x7fffffff;
-    for (int j = lane; j < I.n; j += kWave) {
-      if (!bit_get(vis, j)) {
-        const int64_t d = (int64_t)sqd(xu, I.xy[j]);
-        if (d < bd) {
-          bd = d;
-          bj = j;
-        }
+    return readlane_i(b, ctz64(bm));
+  }
+  // best heuristic value = nearest unvisited city, ties by smaller id
+  cnt[CNT_FALLBACK]++;
+  const int2 xu = I.xy[u];
+  int64_t bd = INT64_MAX;
+  int bj = 0x7fffffff;
+  for (int j = lane; j < I.n; j += kWave) {
+    if (!bit_get(vis, j)) {
+      const int64_t d = (int64_t)sqd(xu, I.xy[j]);
+      if (d < bd) {
+        bd = d;
+        bj = j;
       }
     }
-    const int64_t md = wave_min_i64(bd);
-    v = wave_min_i32(bd == md ? bj : 0x7fffffff);
   }
-  xv = I.xy[v];
+  const int64_t md = wave_min_i64(bd);
+  return wave_min_i32(bd == md ? bj : 0x7fffffff);
+}
+
+// Greedy step of the nearest-neighbour tour: first unvisited candidate
+// (lists are sorted by distance), else the fallback chain.  dv = its cost.
+FACO_DEV int select_greedy(const Inst &I, int u, const uint32_t *vis, int &dv,
+                           int64_t *cnt) {
+  const int K = I.k, lane = lane_id();
+  const size_t row = (size_t)u * (size_t)K;
+  const bool act = lane < K;
+  const int cand = act ? I.cl[row + lane] : 0;
+  const int cd = act ? I.cl_d[row + lane] : 0;
+  const uint64_t um = ballot(act && !bit_get(vis, cand));
+  if (um) {
+    const int s = ctz64(um);
+    dv = readlane_i(cd, s);
+    return readlane_i(cand, s);
+  }
+  const int v = select_fallback(I, u, vis, cnt);
+  dv = cost(I.xy[u], I.xy[v]);
   return v;
 }
 
 // ===================================================================== //
-// Copy-from-source: append source cities in direction `dir` starting after
-// source position pv while they are unvisited, 256 positions per round.
-// Edge costs come from the per-iteration source edge table.
+// Copy-from-source (Alg. 2, reading: forward from v while unvisited, else
+// backward).  The first round probes 64 positions in both directions at
+// once; later rounds take 256 positions.  Edge costs come from the
+// per-iteration source edge table.  Returns the count; u/pu become the last
+// appended city and its source position.
 // ===================================================================== //
-FACO_DEV int copy_run(const Inst &I, int dir, int pv, int &k, int &u,
-                      int64_t &len, int32_t *route, int32_t *pos, uint32_t *vis) {
+FACO_DEV int copy_from(const Inst &I, int pv, int &k, int &u, int &pu, int64_t &len,
+                       int32_t *route, int32_t *pos, uint32_t *vis) {
   const int n = I.n, lane = lane_id();
-  int app = 0, pcur = pv;
+  const int qf = wrap_off(pv, lane + 1, n), qb = wrap_off(pv, -lane - 1, n);
+  const int cf = I.src_route[qf], cb = I.src_route[qb];
+  const int df = I.src_d[qf == 0 ? n - 1 : qf - 1], db = I.src_d[qb];
+  const uint64_t mf = ballot(bit_get(vis, cf));
+  const int jf = mf ? ctz64(mf) : kWave;
+  int dir, j, c, d;
+  if (jf > 0) {
+    dir = 1; j = jf; c = cf; d = df;
+  } else {
+    const uint64_t mb = ballot(bit_get(vis, cb));
+    dir = -1; j = mb ? ctz64(mb) : kWave; c = cb; d = db;
+  }
+  if (j == 0) return 0;
+  if (lane < j) {
+    route[k + lane] = c;
+    pos[c] = k + lane;
+    bit_set(vis, c);
+  }
+  len += wave_sum_i64(lane < j ? (int64_t)d : 0);
+  u = readlane_i(c, j - 1);
+  k += j;
+  int app = j, pcur = wrap_off(pv, dir * j, n);
+  if (j < kWave) {
+    pu = pcur;
+    return app;
+  }
   for (;;) {
-    int c[4], d[4];
+    int cc[4], dd[4];
     bool vc[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int q = wrap_off(pcur, dir * (h * kWave + lane + 1), n);
-      c[h] = I.src_route[q];
-      d[h] = I.src_d[dir > 0 ? (q == 0 ? n - 1 : q - 1) : q];
+      cc[h] = I.src_route[q];
+      dd[h] = I.src_d[dir > 0 ? (q == 0 ? n - 1 : q - 1) : q];
     }
 #pragma unroll
-    for (int h = 0; h < 4; ++h) vc[h] = bit_get(vis, c[h]);
-    int j = 4 * kWave;
+    for (int h = 0; h < 4; ++h) vc[h] = bit_get(vis, cc[h]);
+    int jj = 4 * kWave;
 #pragma unroll
     for (int h = 3; h >= 0; --h) {
       const uint64_t m = ballot(vc[h]);
-      if (m) j = h * kWave + ctz64(m);
+      if (m) jj = h * kWave + ctz64(m);
     }
     int64_t dsum = 0;
     int last = 0;
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int idx = h * kWave + lane;
-      if (idx < j) {
-        route[k + idx] = c[h];
-        pos[c[h]] = k + idx;
-        bit_set(vis, c[h]);
-        dsum += d[h];
+      if (idx < jj) {
+        route[k + idx] = cc[h];
+        pos[cc[h]] = k + idx;
+        bit_set(vis, cc[h]);
+        dsum += dd[h];
       }
-      if (idx == j - 1) last = c[h];
+      if (idx == jj - 1) last = cc[h];
     }
     len += wave_sum_i64(dsum);
-    if (j > 0) u = readlane_i(last, (j - 1) & (kWave - 1));
-    k += j;
-    app += j;
-    pcur = wrapn(pcur + dir * j, n);
-    if (j < 4 * kWave) break;
+    if (jj > 0) u = readlane_i(last, (jj - 1) & (kWave - 1));
+    k += jj;
+    app += jj;
+    pcur = wrapn(pcur + dir * jj, n);
+    if (jj < 4 * kWave) break;
   }
+  pu = pcur;
   return app;
 }
 
 // ===================================================================== //
-// Speculative source-following block.  Lane i evaluates ACO step `step + i`
+// Speculative source-following window.  Lane i evaluates ACO step `step + i`
 // as if the ant had followed the source in direction dir for the previous i
-// steps: its current city is q_i (q_0 = u), its visited set V + {q_1..q_i}
-// (V in LDS, the q's recognised by their source positions).  The first lane
-// whose choice is not q_{i+1} ends the block; its choice is exact because
-// every earlier lane confirmed the assumption.  Same draws, same weights,
-// same order as the one-step-at-a-time rule.
-// Returns the number of steps taken; 0 means step `step` needs the backup
-// list or the nearest-city scan (no candidate unvisited).
+// steps: its current city is q_i (q_0 = u at source position pu), its
+// visited set V + {q_1..q_i} (V in LDS, the q's recognised by their source
+// positions).  The first lane whose choice is not q_{i+1} ends the window;
+// its choice is exact because every earlier lane confirmed the assumption.
+// Same draws, same weights, same order as the one-step-at-a-time rule.
+// Output: acc = steps that followed the source; then, unless the window ran
+// out (v = -2), the decision of step `step + acc`: v with its cost dv and
+// source position pv, or v = -1 when no candidate is unvisited.
 // ===================================================================== //
 template <int KT>
 FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
-                        int u, int dir, int k, int maxw, const uint32_t *vis, int &v,
-                        int &lastq, int64_t &src_len_sum) {
+                        int u, int pu, int dir, int k, int maxw, const uint32_t *vis,
+                        int &v, int &dv, int &pv, int &lastq, int64_t &src_len_sum) {
   const int n = I.n, K = I.k, lane = lane_id();
-  const int p = I.src_pos[u];
-  const int qn = I.src_route[wrap_off(p, dir * (lane + 1), n)];  // q_{lane+1}
+  const int qpos = wrap_off(pu, dir * (lane + 1), n);
+  const int qn = I.src_route[qpos];                 // q_{lane+1}
   const int qu = __shfl_up(qn, 1);
-  const int ui = lane == 0 ? u : qu;                                 // q_lane
-  const int ed = I.src_d[dir > 0 ? wrap_off(p, lane, n) : wrap_off(p, -lane - 1, n)];
+  const int ui = lane == 0 ? u : qu;                 // q_lane
+  const int ed = I.src_d[dir > 0 ? wrap_off(pu, lane, n) : qpos];
   const size_t row = (size_t)ui * (size_t)K;
-  int c[KT], sp[KT];
+  int c[KT], sp[KT], cd[KT];
   float wt[KT];
 #pragma unroll
   for (int s = 0; s < KT; ++s) {
@@ -198,6 +190,7 @@ FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
       c[s] = I.cl[row + s];
       wt[s] = I.w[row + s];
       sp[s] = I.cl_spos[row + s];
+      cd[s] = I.cl_d[row + s];
     }
   }
   // this lane's draw
@@ -208,7 +201,7 @@ FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
 #pragma unroll
   for (int s = 0; s < KT; ++s) {
     if (s < K) {
-      const int off = dir > 0 ? sp[s] - p : p - sp[s];
+      const int off = dir > 0 ? sp[s] - pu : pu - sp[s];
       const int offw = off < 0 ? off + n : off;
       const bool visited = bit_get(vis, c[s]) || (offw >= 1 && offw <= lane);
       if (!visited) {
@@ -219,7 +212,7 @@ FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
     }
   }
   const bool special = last < 0;
-  int choice = 0;
+  int choice = 0, choice_d = 0, choice_p = 0;
   if (!special) {
     const float r = U * total;
     int sel = -1;
@@ -229,7 +222,11 @@ FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
     if (sel < 0) sel = last;
 #pragma unroll
     for (int s = 0; s < KT; ++s)
-      if (s == sel) choice = c[s];
+      if (s == sel) {
+        choice = c[s];
+        choice_d = cd[s];
+        choice_p = sp[s];
+      }
   }
   int valid = n - k < kWave ? n - k : kWave;  // steps left
   valid = valid < maxw ? valid : maxw;
@@ -240,11 +237,12 @@ FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
   src_len_sum = wave_sum_i64(lane < acc ? (int64_t)ed : 0);
   lastq = acc > 0 ? readlane_i(qn, acc - 1) : u;
   if (acc < valid) {
-    // lane acc decides a step off the predicted path
     if (readlane_i(special ? 1 : 0, acc)) {
       v = -1;
     } else {
       v = readlane_i(choice, acc);
+      dv = readlane_i(choice_d, acc);
+      pv = readlane_i(choice_p, acc);
     }
   } else {
     v = -2;  // every step of the window followed the source
@@ -281,35 +279,36 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
                                                     kPurposeStart),
                                        n);
   int u = r0;
-  int2 xu = I.xy[u];
-  const int2 x0 = xu;
   append_city(u, 0, route, pos, vis);
   int k = 1, new_edges = 0;
   nchk = 0;
   int64_t len = 0;
   uint64_t step = 0;
-  DrawWindow DW;
-  DW.valid = false;
-  DW.base = 0;
-  DW.u = 0.0f;
-  int dir = 1;
-  while (k < n) {
-    int v;
-    int2 xv;
-    bool is_new = false;
-    if (!greedy) {
+  if (greedy) {
+    while (k < n) {
+      int dv;
+      const int v = select_greedy(I, u, vis, dv, cnt);
+      ++step;
+      len += dv;
+      append_city(v, k, route, pos, vis);
+      ++k;
+      u = v;
+    }
+  } else {
+    int pu = I.src_pos[u];
+    int dir = 1;
+    while (k < n) {
       // Once new_edges >= m every ACO step is followed by a copy, so the
       // window is one step wide.
       const int maxw = new_edges >= I.m ? 1 : kWave;
-      int lastq;
+      int v, dv = 0, pv = 0, lastq;
       int64_t srcsum;
-      const int acc = spec_block<KT>(I, t, (uint64_t)ant, step, u, dir, k, maxw, vis, v,
-                                     lastq, srcsum);
+      const int acc = spec_block<KT>(I, t, (uint64_t)ant, step, u, pu, dir, k, maxw, vis,
+                                     v, dv, pv, lastq, srcsum);
       if (acc > 0) {
         // accepted steps follow the source: q_1..q_acc at k..k+acc-1
-        const int p = I.src_pos[u];
         if (lane < acc) {
-          const int q = I.src_route[wrap_off(p, dir * (lane + 1), n)];
+          const int q = I.src_route[wrap_off(pu, dir * (lane + 1), n)];
           route[k + lane] = q;
           pos[q] = k + lane;
           bit_set(vis, q);
@@ -317,54 +316,43 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
         k += acc;
         step += acc;
         len += srcsum;
+        pu = wrap_off(pu, dir * acc, n);
         u = lastq;
       }
       if (v == -2) {
         // the whole window followed the source; no step off the path
-        xu = I.xy[u];
         v = u;
-        xv = xu;
+        pv = pu;
       } else {
-        const int2 adj = I.src_adj[u];
-        xu = I.xy[u];
-        if (v >= 0) {
-          xv = I.xy[v];
-        } else {
-          v = select_next(I, u, xu, vis, false, t, (uint64_t)ant, step, DW, xv, cnt);
+        if (v == -1) {
+          v = select_fallback(I, u, vis, cnt);
+          dv = cost(I.xy[u], I.xy[v]);
+          pv = I.src_pos[v];
         }
         ++step;
-        len += cost(xu, xv);
+        len += dv;
         append_city(v, k, route, pos, vis);
         ++k;
-        is_new = v != adj.x && v != adj.y;
-        dir = v == adj.y ? -1 : 1;
+        const int fwd = pu + 1 == n ? 0 : pu + 1, bwd = pu == 0 ? n - 1 : pu - 1;
+        if (pv != fwd && pv != bwd) {
+          ++new_edges;
+          if (lane == 0) {
+            ring[nchk] = v;
+            bit_set(inq, v);
+          }
+          ++nchk;
+        }
+        dir = pv == bwd ? -1 : 1;
       }
-    } else {
-      v = select_next(I, u, xu, vis, true, t, (uint64_t)ant, step, DW, xv, cnt);
-      ++step;
-      len += cost(xu, xv);
-      append_city(v, k, route, pos, vis);
-      ++k;
-    }
-    if (is_new) {
-      ++new_edges;
-      if (lane == 0) {
-        ring[nchk] = v;
-        bit_set(inq, v);
+      u = v;
+      pu = pv;
+      if (new_edges >= I.m && k < n) {
+        const int app = copy_from(I, pv, k, u, pu, len, route, pos, vis);
+        cnt[CNT_COPIED] += app;
       }
-      ++nchk;
-    }
-    u = v;
-    xu = xv;
-    if (!greedy && new_edges >= I.m && k < n) {
-      const int pv = I.src_pos[v];
-      int app = copy_run(I, +1, pv, k, u, len, route, pos, vis);
-      if (app == 0) app = copy_run(I, -1, pv, k, u, len, route, pos, vis);
-      if (app) xu = I.xy[u];
-      cnt[CNT_COPIED] += app;
     }
   }
-  len += cost(xu, x0);
+  len += cost(I.xy[u], I.xy[r0]);
   cnt[CNT_ACO_STEPS] += (int64_t)step;
   cnt[CNT_NEW_EDGES] += new_edges;
   wave_fence();
@@ -641,7 +629,7 @@ FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
   return found;
 }
 
-constexpr int kChunks = 8;  // 64-element chunks in flight per round
+constexpr int kChunks = 16;  // 64-element chunks in flight per round
 
 // Reverse the cyclic array range of length L starting at s (wave-wide).
 FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos) {
@@ -1172,7 +1160,7 @@ constexpr int kKnnTile = 256;
 
 __global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, int n, int K, int BL,
                                                  int32_t *cl, int32_t *bll, float *eta,
-                                                 DevState *st) {
+                                                 int32_t *cl_d, DevState *st) {
   extern __shared__ unsigned char knn_lds[];
   const int KK = K + BL;
   const int tid = threadIdx.x;
@@ -1213,6 +1201,7 @@ __global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, int n, int K, i
     const double d2 = kd[s * 64 + tid];
     cl[(size_t)i * K + s] = kj[s * 64 + tid];
     const int d = (int)floor(sqrt(d2) + 0.5);
+    cl_d[(size_t)i * K + s] = d;
     eta[(size_t)i * K + s] = (float)(1.0 / (double)d);
   }
   for (int s = 0; s < BL; ++s) bll[(size_t)i * BL + s] = kj[(K + s) * 64 + tid];

@@ -54,6 +54,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise FacoError(FACO_EDEVICE, f"{LIB_PATH} is not built (run build())")
+        # PyTorch brings its own HIP runtime; loading it first makes the
+        # library bind to that same runtime, so torch streams and events and
+        # the library's launches share one runtime in the process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, P = ctypes.c_void_p, ctypes.POINTER
         L.faco_build_instance.restype = ctypes.c_int
