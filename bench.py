@@ -281,9 +281,14 @@ def main():
     F.faco_set_timing(g, False)
     tot1 = F.faco_debug_get(g, F.FACO_DBG_COUNTER_TOTALS)
     tk = (F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS) - tk0).astype(np.float64)
-    # per ant and iteration, microseconds (100 MHz wall clock)
-    tk_us = {name: round(float(tk[:, i].mean()) / args.steps / 100.0, 1) for i, name in
-             enumerate(["construct", "ls_eval", "ls_apply", "sweep", "ant_total"])}
+    # per ant and iteration: microseconds (100 MHz wall clock) and call counts
+    per = tk.mean(0) / args.steps
+    tk_us = {name: round(float(per[i]) / 100.0, 1) for i, name in
+             [(0, "construct"), (1, "ls_eval"), (2, "ls_apply"), (3, "sweep"), (4, "ant_total"),
+              (8, "spec_windows"), (9, "one_steps"), (10, "copies"), (11, "fallbacks")]}
+    tk_calls = {name: round(float(per[i]), 1) for i, name in
+                [(5, "spec_windows"), (6, "one_steps"), (7, "copies"), (12, "eval_rounds")]}
+    slowest_us = round(float(tk[:, 4].max()) / args.steps / 100.0, 1)
     bytes_ant = float(algorithmic_bytes_per_ant(tot1 - tot0, n, k, bl).sum())
     cnt_mean = ((tot1 - tot0).sum(0) / (A * args.steps)).tolist()
     best_tour, best_len = F.faco_get_best_tour(g)
@@ -313,6 +318,8 @@ def main():
                    f"{args.warmup + 1}..{args.warmup + args.steps}",
                    "best_length": int(best_len), "iterations_done": int(info[0])},
         "per_ant_us": tk_us,
+        "per_ant_calls": tk_calls,
+        "slowest_ant_us": slowest_us,
         "per_ant_counters": {name: round(v, 1) for name, v in zip(F.CNT_NAMES, cnt_mean)},
         "phase_ms_per_iteration": {name: round(phase_ms[i] / max(1, launches[i]), 4)
                                    for i, name in enumerate(["ants", "colony", "source",

@@ -141,10 +141,14 @@ enum {
   FACO_DBG_INIT_COUNTERS = 10, /* int64 [FACO_NCNT] of the initial solution  */
   FACO_DBG_COUNTER_TOTALS = 11, /* int64 [n_ants][FACO_NCNT], summed over all
                                    iterations since the build                 */
-  FACO_DBG_PHASE_TICKS = 12 /* int64 [n_ants][8] device wall-clock ticks
-                               (100 MHz) summed since the build: [0]
+  FACO_DBG_PHASE_TICKS = 12 /* int64 [n_ants][16] summed since the build;
+                               device wall-clock ticks (100 MHz): [0]
                                construction, [1] move evaluation, [2] move
-                               application, [3] sweeps, [4] whole ant        */
+                               application, [3] sweeps, [4] whole ant, [8]
+                               speculative windows, [9] one-step choices,
+                               [10] copies, [11] backup/nearest choices; call
+                               counts: [5] windows, [6] one-step choices, [7]
+                               copies, [12] evaluation rounds             */
 };
 /* per-ant counters (same meaning as the oracle's) */
 enum {

@@ -86,15 +86,30 @@ FACO_DEV void bit_clear(uint32_t *bm, int x) {
 
 // ---------------------------------------------------------------- cost ---
 // TSPLIB EUC_2D: nint(sqrt(dx^2 + dy^2)).  With |dx|,|dy| < 2^23 the squared
-// length is an exact binary64 integer and the rounded square root decides
-// nint exactly (no integer is within one ulp of a half-integer square root).
+// length is an exact integer below 2^47.  A binary32 square root estimates
+// floor(sqrt(d2)) to within 2; integer checks make it exact, and nint is
+// r + [d2 > r^2 + r] (sqrt(d2) is never exactly a half-integer).
 
 FACO_DEV double sqd(int2 a, int2 b) {
   double dx = (double)(a.x - b.x);
   double dy = (double)(a.y - b.y);
   return dx * dx + dy * dy;
 }
-FACO_DEV int cost(int2 a, int2 b) { return (int)floor(sqrt(sqd(a, b)) + 0.5); }
+FACO_DEV uint64_t sqd_u64(int2 a, int2 b) {
+  const int dx = a.x - b.x, dy = a.y - b.y;
+  const uint32_t ax = (uint32_t)(dx < 0 ? -dx : dx), ay = (uint32_t)(dy < 0 ? -dy : dy);
+  return (uint64_t)ax * ax + (uint64_t)ay * ay;
+}
+FACO_DEV int cost(int2 a, int2 b) {
+  const uint64_t d2 = sqd_u64(a, b);
+  // estimate within [floor - 2, floor + 1] (binary32: relative error < 2^-23)
+  uint32_t r = (uint32_t)__fsqrt_rn((float)d2);
+  r -= ((uint64_t)r * r > d2) ? 1u : 0u;
+  r -= ((uint64_t)r * r > d2) ? 1u : 0u;
+  r += ((uint64_t)(r + 1) * (r + 1) <= d2) ? 1u : 0u;
+  r += ((uint64_t)(r + 1) * (r + 1) <= d2) ? 1u : 0u;
+  return (int)r + (d2 > (uint64_t)r * r + r ? 1 : 0);
+}
 
 // ----------------------------------------------------------- Philox4x64 ---
 // Salmon et al., SC'11: 10 rounds, multipliers M0, M1, Weyl key increments.

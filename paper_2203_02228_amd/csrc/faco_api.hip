@@ -89,11 +89,11 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   const uint64_t N = (uint64_t)n, A = (uint64_t)p->n_ants;
   uint64_t b = 0;
   b += align_up(8 * N);                    // xy
-  b += 6 * align_up(4 * N * (uint64_t)k);  // cl, cost, eta, tau, tau*eta, candidate source positions
+  b += 8 * align_up(4 * N * (uint64_t)k);  // cl, cost, eta, tau + source-ordered rows (city, weight, position, cost)
   b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
   b += 4 * align_up(4 * N) + align_up(8 * N); // source route/pos/edge costs, adjacency, global best
-  b += 3 * align_up(4 * N * A);            // ant routes, pos, checklist rings
-  b += align_up(8 * A) + 2 * align_up(8 * A * faco::NCNT) + align_up(64 * A);
+  b += 3 * align_up(4 * N * A) + align_up(8 * N * A);  // ant routes, pos, rings, tour coordinates
+  b += align_up(8 * A) + 2 * align_up(8 * A * faco::NCNT) + align_up(128 * A);
   b += align_up(sizeof(DevState));
   return b;
 }
@@ -209,8 +209,10 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   ALLOC(eta, float, N * K);
   ALLOC(cl_d, int32_t, N * K);
   ALLOC(tau, float, N * K);
-  ALLOC(w, float, N * K);
-  ALLOC(cl_spos, int32_t, N * K);
+  ALLOC(scl, int32_t, N * K);
+  ALLOC(sw, float, N * K);
+  ALLOC(ssp, int32_t, N * K);
+  ALLOC(sd, int32_t, N * K);
   ALLOC(src_route, int32_t, N);
   ALLOC(src_pos, int32_t, N);
   ALLOC(gb_route, int32_t, N);
@@ -219,10 +221,11 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   ALLOC(routes, int32_t, N * A);
   ALLOC(pos, int32_t, N * A);
   ALLOC(ring, int32_t, N * A);
+  ALLOC(rxy, int2, N * A);
   ALLOC(lens, int64_t, A);
   ALLOC(cnt, int64_t, A * faco::NCNT);
   ALLOC(cnt_acc, int64_t, A * faco::NCNT);
-  ALLOC(ticks, int64_t, A * 8);
+  ALLOC(ticks, int64_t, A * 16);
   ALLOC(st, DevState, 1);
 #undef ALLOC
 
@@ -240,7 +243,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   }
   BTRY(hipMemsetAsync(I.st, 0, sizeof(DevState), h->stream));
   BTRY(hipMemsetAsync(I.cnt_acc, 0, sizeof(int64_t) * A * faco::NCNT, h->stream));
-  BTRY(hipMemsetAsync(I.ticks, 0, sizeof(int64_t) * A * 8, h->stream));
+  BTRY(hipMemsetAsync(I.ticks, 0, sizeof(int64_t) * A * 16, h->stream));
   BTRY(hipMemcpyAsync((void *)I.xy, xy, sizeof(int2) * N, hipMemcpyHostToDevice, h->stream));
 
   const size_t klds = knn_lds_bytes(h->k, h->bl);
@@ -331,7 +334,7 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
     case FACO_DBG_SOURCE: src = h->dv.src_route; need = 4 * N; break;
     case FACO_DBG_COUNTERS: src = h->dv.cnt; need = 8 * A * faco::NCNT; break;
     case FACO_DBG_COUNTER_TOTALS: src = h->dv.cnt_acc; need = 8 * A * faco::NCNT; break;
-    case FACO_DBG_PHASE_TICKS: src = h->dv.ticks; need = 8 * A * 8; break;
+    case FACO_DBG_PHASE_TICKS: src = h->dv.ticks; need = 8 * A * 16; break;
     case FACO_DBG_CAND_LISTS: src = h->dv.cl; need = 4 * N * K; break;
     case FACO_DBG_BACKUP_LISTS: src = h->dv.bll; need = 4 * N * BL; break;
     case FACO_DBG_HEURISTIC: src = h->dv.eta; need = 4 * N * K; break;

@@ -44,12 +44,17 @@ struct Inst {
   float *tau;
   int32_t *src_route, *src_pos, *gb_route;
   int2 *src_adj;      // [n] (successor, predecessor) of each city in the source
-  float *w;           // [n][k] tau * eta of every candidate slot (this iteration)
-  int32_t *cl_spos;   // [n][k] source position of every candidate (this iteration)
+  // Candidate rows in SOURCE order (row p = candidates of the city at source
+  // position p), rewritten by the pheromone kernel every iteration:
+  int32_t *scl;       // [n][k] candidate city
+  float *sw;          // [n][k] tau * eta (Eq. (1) weight)
+  int32_t *ssp;       // [n][k] source position of the candidate
+  int32_t *sd;        // [n][k] cost of the candidate edge
   int32_t *src_d;     // [n] cost of the source edge from position i to i + 1
   int32_t *routes, *pos, *ring;
+  int2 *rxy;          // [A][n] coordinates of routes[a][p] (tour order)
   int64_t *lens, *cnt, *cnt_acc;
-  int64_t *ticks;     // [A][8] wall-clock ticks per phase, summed
+  int64_t *ticks;     // [A][16] wall-clock ticks and call counts per phase, summed
   DevState *st;
 };
 

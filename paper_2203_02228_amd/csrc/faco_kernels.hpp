@@ -11,9 +11,21 @@
 
 namespace faco {
 
+// q mod n; the common cases (q within one period of [0, n)) avoid a division
+FACO_DEV int64_t ticks() { return (int64_t)wall_clock64(); }
+
 FACO_DEV int wrapn(int q, int n) {
-  q %= n;
-  return q < 0 ? q + n : q;
+  if (q >= n) {
+    q -= n;
+    if (q >= n) q %= n;
+  } else if (q < 0) {
+    q += n;
+    if (q < 0) {
+      q %= n;
+      q = q < 0 ? q + n : q;
+    }
+  }
+  return q;
 }
 // for 0 <= q < 2n
 FACO_DEV int wrap1(int q, int n) { return q >= n ? q - n : q; }
@@ -44,14 +56,21 @@ FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, int64_t 
     cnt[CNT_BACKUP]++;
     return readlane_i(b, ctz64(bm));
   }
-  // best heuristic value = nearest unvisited city, ties by smaller id
+  // best heuristic value = nearest unvisited city, ties by smaller id.
+  // Lane l scans bitmap words l, l + 64, ...; fully visited words are skipped.
   cnt[CNT_FALLBACK]++;
   const int2 xu = I.xy[u];
+  const int W = (I.n + 31) >> 5;
   int64_t bd = INT64_MAX;
   int bj = 0x7fffffff;
-  for (int j = lane; j < I.n; j += kWave) {
-    if (!bit_get(vis, j)) {
-      const int64_t d = (int64_t)sqd(xu, I.xy[j]);
+  for (int w = lane; w < W; w += kWave) {
+    uint32_t free_bits = ~vis[w];
+    const int rem = I.n - w * 32;
+    if (rem < 32) free_bits &= (1u << rem) - 1u;
+    while (free_bits) {
+      const int j = w * 32 + __builtin_ctz(free_bits);
+      free_bits &= free_bits - 1;
+      const int64_t d = (int64_t)sqd_u64(xu, I.xy[j]);
       if (d < bd) {
         bd = d;
         bj = j;
@@ -90,7 +109,7 @@ FACO_DEV int select_greedy(const Inst &I, int u, const uint32_t *vis, int &dv,
 // appended city and its source position.
 // ===================================================================== //
 FACO_DEV int copy_from(const Inst &I, int pv, int &k, int &u, int &pu, int64_t &len,
-                       int32_t *route, int32_t *pos, uint32_t *vis) {
+                       int32_t *route, int32_t *pos, int2 *rxy, uint32_t *vis) {
   const int n = I.n, lane = lane_id();
   const int qf = wrap_off(pv, lane + 1, n), qb = wrap_off(pv, -lane - 1, n);
   const int cf = I.src_route[qf], cb = I.src_route[qb];
@@ -108,6 +127,7 @@ FACO_DEV int copy_from(const Inst &I, int pv, int &k, int &u, int &pu, int64_t &
   if (lane < j) {
     route[k + lane] = c;
     pos[c] = k + lane;
+    rxy[k + lane] = I.xy[c];
     bit_set(vis, c);
   }
   len += wave_sum_i64(lane < j ? (int64_t)d : 0);
@@ -143,6 +163,7 @@ FACO_DEV int copy_from(const Inst &I, int pv, int &k, int &u, int &pu, int64_t &
       if (idx < jj) {
         route[k + idx] = cc[h];
         pos[cc[h]] = k + idx;
+        rxy[k + idx] = I.xy[cc[h]];
         bit_set(vis, cc[h]);
         dsum += dd[h];
       }
@@ -171,30 +192,45 @@ FACO_DEV int copy_from(const Inst &I, int pv, int &k, int &u, int &pu, int64_t &
 // out (v = -2), the decision of step `step + acc`: v with its cost dv and
 // source position pv, or v = -1 when no candidate is unvisited.
 // ===================================================================== //
+struct Draws {
+  uint64_t base;  // lane j holds the roulette draw of step base + j
+  float u;
+  bool valid;
+};
+
 template <int KT>
 FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
                         int u, int pu, int dir, int k, int maxw, const uint32_t *vis,
-                        int &v, int &dv, int &pv, int &lastq, int64_t &src_len_sum) {
+                        Draws &D, int &v, int &dv, int &pv, int &lastq,
+                        int64_t &src_len_sum) {
   const int n = I.n, K = I.k, lane = lane_id();
+  // every load below is addressed by source position: one round trip
+  const int rpos = wrap_off(pu, dir * lane, n);      // position of q_lane
   const int qpos = wrap_off(pu, dir * (lane + 1), n);
-  const int qn = I.src_route[qpos];                 // q_{lane+1}
-  const int qu = __shfl_up(qn, 1);
-  const int ui = lane == 0 ? u : qu;                 // q_lane
-  const int ed = I.src_d[dir > 0 ? wrap_off(pu, lane, n) : qpos];
-  const size_t row = (size_t)ui * (size_t)K;
+  const int qn = I.src_route[qpos];                   // q_{lane+1}
+  const int ed = I.src_d[dir > 0 ? rpos : qpos];      // cost q_lane -> q_{lane+1}
+  const size_t row = (size_t)rpos * (size_t)K;
   int c[KT], sp[KT], cd[KT];
   float wt[KT];
 #pragma unroll
   for (int s = 0; s < KT; ++s) {
     if (s < K) {
-      c[s] = I.cl[row + s];
-      wt[s] = I.w[row + s];
-      sp[s] = I.cl_spos[row + s];
-      cd[s] = I.cl_d[row + s];
+      c[s] = I.scl[row + s];
+      wt[s] = I.sw[row + s];
+      sp[s] = I.ssp[row + s];
+      cd[s] = I.sd[row + s];
     }
   }
-  // this lane's draw
-  const float U = unit24(philox_word0(I.seed, t, ant, step + (uint64_t)lane, kPurposeRoulette));
+  // draws: a one-step window reuses the 64 draws computed for earlier steps
+  float U;
+  if (maxw == 1 && D.valid && step >= D.base && step < D.base + kWave) {
+    U = readlane_f(D.u, (int)(step - D.base));
+  } else {
+    D.u = unit24(philox_word0(I.seed, t, ant, step + (uint64_t)lane, kPurposeRoulette));
+    D.base = step;
+    D.valid = true;
+    U = D.u;
+  }
   float P[KT];
   float total = 0.0f;
   int last = -1;
@@ -250,24 +286,65 @@ FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
   return acc;
 }
 
+// One ACO step from the city at source position pu, lane s = candidate slot
+// s (used once new_edges >= m, when every step is followed by a copy).
+// v = -1 when no candidate is unvisited.
+FACO_DEV int one_step(const Inst &I, uint64_t t, uint64_t ant, uint64_t step, int pu,
+                      const uint32_t *vis, Draws &D, int &dv, int &pv) {
+  const int n = I.n, K = I.k, lane = lane_id();
+  (void)n;
+  const bool act = lane < K;
+  const size_t row = (size_t)pu * (size_t)K;
+  const int c = act ? I.scl[row + lane] : 0;
+  const float w = act ? I.sw[row + lane] : 0.0f;
+  const int sp = act ? I.ssp[row + lane] : 0;
+  const int d = act ? I.sd[row + lane] : 0;
+  const bool unv = act && !bit_get(vis, c);
+  const uint64_t um = ballot(unv);
+  if (!um) return -1;
+  if (!(D.valid && step >= D.base && step < D.base + kWave)) {
+    D.u = unit24(philox_word0(I.seed, t, ant, step + (uint64_t)lane, kPurposeRoulette));
+    D.base = step;
+    D.valid = true;
+  }
+  const float U = readlane_f(D.u, (int)(step - D.base));
+  const float wv = unv ? w : 0.0f;
+  // cumulative sum in slot order: lane s holds fl(...fl(w_0 + w_1)... + w_s)
+  float P = 0.0f;
+  for (int j = 0; j < K; ++j) {
+    const float wj = readlane_f(wv, j);
+    if (j <= lane) P = P + wj;
+  }
+  const float r = U * readlane_f(P, K - 1);
+  const uint64_t sm = ballot(act && P > r);
+  const int s = sm ? ctz64(sm) : msb64(um);
+  dv = readlane_i(d, s);
+  pv = readlane_i(sp, s);
+  return readlane_i(c, s);
+}
+
 // ===================================================================== //
 // Focused construction (Alg. 2 inner loop).  greedy: nearest-neighbour tour
 // from city 0 (initial solution), no source, no copy.
 // The checklist is written into ring[0..nchk) with its LDS bits set in inq.
 // ===================================================================== //
-FACO_DEV void append_city(int v, int k, int32_t *route, int32_t *pos, uint32_t *vis) {
+FACO_DEV void append_city(const Inst &I, int v, int k, int32_t *route, int32_t *pos,
+                          int2 *rxy, uint32_t *vis) {
   if (lane_id() == 0) {
     route[k] = v;
     pos[v] = k;
+    rxy[k] = I.xy[v];
     bit_set(vis, v);
   }
 }
 
+// tk: [5] speculative windows, [6] one-step calls, [7] copies, [8..10] their
+// ticks, [11] ticks in backup/nearest-city choices
 template <int KT>
 FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
-                           int32_t *route, int32_t *pos, int32_t *ring,
+                           int32_t *route, int32_t *pos, int2 *rxy, int32_t *ring,
                            uint32_t *vis, uint32_t *inq, int W, int &nchk,
-                           int64_t *cnt) {
+                           int64_t *cnt, int64_t *tk) {
   const int n = I.n, lane = lane_id();
   for (int w = lane; w < W; w += kWave) {
     vis[w] = 0u;
@@ -279,7 +356,7 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
                                                     kPurposeStart),
                                        n);
   int u = r0;
-  append_city(u, 0, route, pos, vis);
+  append_city(I, u, 0, route, pos, rxy, vis);
   int k = 1, new_edges = 0;
   nchk = 0;
   int64_t len = 0;
@@ -290,27 +367,42 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
       const int v = select_greedy(I, u, vis, dv, cnt);
       ++step;
       len += dv;
-      append_city(v, k, route, pos, vis);
+      append_city(I, v, k, route, pos, rxy, vis);
       ++k;
       u = v;
     }
   } else {
     int pu = I.src_pos[u];
     int dir = 1;
+    Draws D;
+    D.base = 0;
+    D.u = 0.0f;
+    D.valid = false;
     while (k < n) {
       // Once new_edges >= m every ACO step is followed by a copy, so the
       // window is one step wide.
       const int maxw = new_edges >= I.m ? 1 : kWave;
-      int v, dv = 0, pv = 0, lastq;
-      int64_t srcsum;
-      const int acc = spec_block<KT>(I, t, (uint64_t)ant, step, u, pu, dir, k, maxw, vis,
-                                     v, dv, pv, lastq, srcsum);
+      int v, dv = 0, pv = 0, lastq = u;
+      int64_t srcsum = 0;
+      int acc = 0;
+      const int64_t c0 = ticks();
+      if (maxw == 1) {
+        v = one_step(I, t, (uint64_t)ant, step, pu, vis, D, dv, pv);
+        tk[6]++;
+        tk[9] += ticks() - c0;
+      } else {
+        acc = spec_block<KT>(I, t, (uint64_t)ant, step, u, pu, dir, k, maxw, vis, D, v, dv,
+                             pv, lastq, srcsum);
+        tk[5]++;
+        tk[8] += ticks() - c0;
+      }
       if (acc > 0) {
         // accepted steps follow the source: q_1..q_acc at k..k+acc-1
         if (lane < acc) {
           const int q = I.src_route[wrap_off(pu, dir * (lane + 1), n)];
           route[k + lane] = q;
           pos[q] = k + lane;
+          rxy[k + lane] = I.xy[q];
           bit_set(vis, q);
         }
         k += acc;
@@ -325,13 +417,15 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
         pv = pu;
       } else {
         if (v == -1) {
+          const int64_t c1 = ticks();
           v = select_fallback(I, u, vis, cnt);
           dv = cost(I.xy[u], I.xy[v]);
           pv = I.src_pos[v];
+          tk[11] += ticks() - c1;
         }
         ++step;
         len += dv;
-        append_city(v, k, route, pos, vis);
+        append_city(I, v, k, route, pos, rxy, vis);
         ++k;
         const int fwd = pu + 1 == n ? 0 : pu + 1, bwd = pu == 0 ? n - 1 : pu - 1;
         if (pv != fwd && pv != bwd) {
@@ -347,8 +441,11 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
       u = v;
       pu = pv;
       if (new_edges >= I.m && k < n) {
-        const int app = copy_from(I, pv, k, u, pu, len, route, pos, vis);
+        const int64_t c2 = ticks();
+        const int app = copy_from(I, pv, k, u, pu, len, route, pos, rxy, vis);
         cnt[CNT_COPIED] += app;
+        tk[7]++;
+        tk[10] += ticks() - c2;
       }
     }
   }
@@ -370,6 +467,7 @@ struct Move {
   int f, l, p, q, a, o, b, e, L;  // Or-opt
   int fpos, pq, pp, pb, side;     // positions of f, q, p, b; e = succ(b) if side 0
   int s0, s1, s2;     // segment in array order
+  int2 xs0, xs1, xs2; // and its coordinates
 };
 
 // Or-opt variants in evaluation order, one fixed slot each:
@@ -404,8 +502,8 @@ FACO_DEV int64_t group_max(int64_t v) {
 // Per-lane state of a grouped evaluation: GS lanes evaluate one city a
 // (slot s = lane % GS handles candidate s), 64 / GS cities per wave.
 struct GroupEval {
-  int a, pa, b, pb, pbs, pbp, bs, bp, nb;
-  int2 xa, xnb;
+  int a, pa, b, pb, pbs, pbp, bs, bp, nb, d_ab;
+  int2 xa, xnb, xb, xbs, xbp;
   int64_t key2, keyo;  // group maxima: 2-opt, Or-opt (0 = none)
 };
 
@@ -415,7 +513,7 @@ struct GroupEval {
 // variants, list slots, succ before pred.
 template <int GS>
 FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
-                              const int32_t *route, const int32_t *pos) {
+                              const int32_t *route, const int32_t *pos, const int2 *rxy) {
   const int n = I.n, K = I.k, lane = lane_id();
   const int gb = lane & ~(GS - 1);
   const int s = lane & (GS - 1);
@@ -426,21 +524,21 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
   // level 1: indexed by a
   const int pa = pos[a];
   const int b = act ? I.cl[row + s] : a;
+  const int d_ab = act ? I.cl_d[row + s] : 0;
   const int2 xa = I.xy[a];
   // level 2
-  const int nb = s < 7 ? route[wrapn(pa + s - 3, n)] : a;
+  const int pn = wrapn(pa + s - 3, n);
+  const int nb = s < 7 ? route[pn] : a;
+  const int2 xnb = s < 7 ? rxy[pn] : xa;
   const int pb = pos[b];
   const int2 xb = I.xy[b];
   // level 3
   const int pbs = pb + 1 == n ? 0 : pb + 1, pbp = pb == 0 ? n - 1 : pb - 1;
   const int bs = route[pbs], bp = route[pbp];
-  const int2 xnb = I.xy[nb];
-  // level 4
-  const int2 xbs = I.xy[bs], xbp = I.xy[bp];
+  const int2 xbs = rxy[pbs], xbp = rxy[pbp];
   R.pa = pa; R.b = b; R.pb = pb; R.pbs = pbs; R.pbp = pbp; R.bs = bs; R.bp = bp;
-  R.nb = nb; R.xa = xa; R.xnb = xnb;
+  R.nb = nb; R.xa = xa; R.xnb = xnb; R.xb = xb; R.xbs = xbs; R.xbp = xbp; R.d_ab = d_ab;
   const int2 xas = shfl_i2(xnb, gb + 4), xap = shfl_i2(xnb, gb + 2);
-  const int d_ab = cost(xa, xb);
   R.key2 = 0;
   if (flags & LS_2OPT) {
     const int d_as = cost(xa, xas), d_ap = cost(xap, xa);
@@ -452,43 +550,52 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
     R.key2 = group_max<GS>(k1 > k2 ? k1 : k2);
   }
   R.keyo = 0;
-  if (flags & LS_OROPT) {
-    const int Lmax = or_lmax(I);
-    int lbest = 0, lidx = 0;
-    const int d_bs = cost(xb, xbs), d_bp = cost(xb, xbp);
+  return R;
+}
+
+// Or-opt keys for the cities of the groups with `want` set (the others get 0).
+template <int GS>
+FACO_DEV void eval_group_oropt(const Inst &I, bool want, GroupEval &R) {
+  const int n = I.n, K = I.k, lane = lane_id();
+  const int gb = lane & ~(GS - 1);
+  const int s = lane & (GS - 1);
+  const bool act = want && s < K;
+  const int pa = R.pa, pb = R.pb, pbs = R.pbs, pbp = R.pbp, d_ab = R.d_ab;
+  const int2 xa = R.xa, xnb = R.xnb, xb = R.xb, xbs = R.xbs, xbp = R.xbp;
+  const int Lmax = or_lmax(I);
+  int lbest = 0, lidx = 0;
+  const int d_bs = cost(xb, xbs), d_bp = cost(xb, xbp);
 #pragma unroll
-    for (int vi = 0; vi < kOrSlots; ++vi) {
-      int dir, L, lf, ll, lp, lq;
-      or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
-      if (L > Lmax) continue;
-      const int2 xf = shfl_i2(xnb, gb + lf), xl = shfl_i2(xnb, gb + ll);
-      const int2 xp = shfl_i2(xnb, gb + lp), xq = shfl_i2(xnb, gb + lq);
-      const int2 xo = dir == 0 ? xl : xf;
-      const int fpos = dir == 0 ? pa : wrapn(pa - L + 1, n);
-      const int rem_a = dir == 0 ? cost(xp, xa) : cost(xa, xq);
-      const int g_rem = cost(xp, xf) + cost(xl, xq) - cost(xp, xq);
-      if (!act) continue;
-      if (wrapn(pb - fpos, n) < L) continue;
-      if (!(d_ab < rem_a)) continue;
-      if (wrapn(pbs - fpos, n) >= L) {
-        const int g = g_rem + d_bs - d_ab - cost(xo, xbs);
-        if (g > lbest) {
-          lbest = g;
-          lidx = (vi * K + s) * 2 + 0;
-        }
-      }
-      if (wrapn(pbp - fpos, n) >= L) {
-        const int g = g_rem + d_bp - d_ab - cost(xo, xbp);
-        if (g > lbest) {
-          lbest = g;
-          lidx = (vi * K + s) * 2 + 1;
-        }
+  for (int vi = 0; vi < kOrSlots; ++vi) {
+    int dir, L, lf, ll, lp, lq;
+    or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
+    if (L > Lmax) continue;
+    const int2 xf = shfl_i2(xnb, gb + lf), xl = shfl_i2(xnb, gb + ll);
+    const int2 xp = shfl_i2(xnb, gb + lp), xq = shfl_i2(xnb, gb + lq);
+    const int2 xo = dir == 0 ? xl : xf;
+    const int fpos = dir == 0 ? pa : wrapn(pa - L + 1, n);
+    const int rem_a = dir == 0 ? cost(xp, xa) : cost(xa, xq);
+    if (!act) continue;
+    if (!(d_ab < rem_a)) continue;
+    if (wrapn(pb - fpos, n) < L) continue;
+    const int g_rem = cost(xp, xf) + cost(xl, xq) - cost(xp, xq);
+    if (wrapn(pbs - fpos, n) >= L) {
+      const int g = g_rem + d_bs - d_ab - cost(xo, xbs);
+      if (g > lbest) {
+        lbest = g;
+        lidx = (vi * K + s) * 2 + 0;
       }
     }
-    const int64_t key = lbest > 0 ? (((int64_t)lbest << 16) | (int64_t)(0xFFFF - lidx)) : 0;
-    R.keyo = group_max<GS>(key);
+    if (wrapn(pbp - fpos, n) >= L) {
+      const int g = g_rem + d_bp - d_ab - cost(xo, xbp);
+      if (g > lbest) {
+        lbest = g;
+        lidx = (vi * K + s) * 2 + 1;
+      }
+    }
   }
-  return R;
+  const int64_t key = lbest > 0 ? (((int64_t)lbest << 16) | (int64_t)(0xFFFF - lidx)) : 0;
+  R.keyo = group_max<GS>(key);
 }
 
 // The move found for the city of group j (uniform j), from the group's lanes.
@@ -548,58 +655,65 @@ FACO_DEV Move extract_move(const Inst &I, const GroupEval &R, int j) {
   mv.s0 = readlane_i(R.nb, base + lf);
   mv.s1 = readlane_i(R.nb, base + lf + (L > 1 ? 1 : 0));
   mv.s2 = readlane_i(R.nb, base + lf + (L > 2 ? 2 : 0));
+  mv.xs0 = readlane_i2(R.xnb, base + lf);
+  mv.xs1 = readlane_i2(R.xnb, base + lf + (L > 1 ? 1 : 0));
+  mv.xs2 = readlane_i2(R.xnb, base + lf + (L > 2 ? 2 : 0));
   return mv;
 }
 
 // Lane-serial test used by the sweep (one city per lane): does x have an
-// improving move?  All loads are issued before any gain is formed.
+// improving move?  Loads are issued before gains are formed; candidate lists
+// are sorted by distance, so a slot that fails the pruning test ends the scan.
 template <int KT>
 FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
-                            const int32_t *route, const int32_t *pos) {
+                            const int32_t *route, const int32_t *pos, const int2 *rxy) {
   const int n = I.n, K = I.k;
   const size_t row = (size_t)x * (size_t)K;
   const int px = pos[x];
-  int b[KT];
+  int b[KT], dxb[KT];
 #pragma unroll
-  for (int s = 0; s < KT; ++s) b[s] = s < K ? I.cl[row + s] : x;
+  for (int s = 0; s < KT; ++s) {
+    b[s] = s < K ? I.cl[row + s] : x;
+    dxb[s] = s < K ? I.cl_d[row + s] : 0;
+  }
   const int2 cx = I.xy[x];
-  int nbv[7];
+  int xnx[7], xny[7];
 #pragma unroll
-  for (int j = 0; j < 7; ++j) nbv[j] = route[wrapn(px + j - 3, n)];
-  int pb[KT];
-  int2 xb[KT];
+  for (int j = 0; j < 7; ++j) {
+    const int2 q = rxy[wrapn(px + j - 3, n)];
+    xnx[j] = q.x; xny[j] = q.y;
+  }
+  int pb[KT], xbx[KT], xby[KT];
 #pragma unroll
   for (int s = 0; s < KT; ++s) {
     pb[s] = pos[b[s]];
-    xb[s] = I.xy[b[s]];
+    const int2 q = I.xy[b[s]];
+    xbx[s] = q.x; xby[s] = q.y;
   }
-  int2 xn[7];
-#pragma unroll
-  for (int j = 0; j < 7; ++j) xn[j] = I.xy[nbv[j]];
-  int bs[KT], bp[KT];
+  int xbsx[KT], xbsy[KT], xbpx[KT], xbpy[KT];
 #pragma unroll
   for (int s = 0; s < KT; ++s) {
-    bs[s] = route[pb[s] + 1 == n ? 0 : pb[s] + 1];
-    bp[s] = route[pb[s] == 0 ? n - 1 : pb[s] - 1];
+    const int2 q1 = rxy[pb[s] + 1 == n ? 0 : pb[s] + 1];
+    const int2 q2 = rxy[pb[s] == 0 ? n - 1 : pb[s] - 1];
+    xbsx[s] = q1.x; xbsy[s] = q1.y;
+    xbpx[s] = q2.x; xbpy[s] = q2.y;
   }
-  int2 xbs[KT], xbp[KT];
-#pragma unroll
-  for (int s = 0; s < KT; ++s) {
-    xbs[s] = I.xy[bs[s]];
-    xbp[s] = I.xy[bp[s]];
-  }
-  bool found = false;
+#define XN(j) make_int2(xnx[j], xny[j])
+#define XB(s) make_int2(xbx[s], xby[s])
+#define XBS(s) make_int2(xbsx[s], xbsy[s])
+#define XBP(s) make_int2(xbpx[s], xbpy[s])
   if (flags & LS_2OPT) {
-    const int d_s = cost(cx, xn[4]), d_p = cost(xn[2], cx);
+    const int d_s = cost(cx, XN(4)), d_p = cost(XN(2), cx);
 #pragma unroll
     for (int s = 0; s < KT; ++s) {
-      if (s >= K) continue;
-      const int d_xb = cost(cx, xb[s]);
-      if (d_s > d_xb && d_s + cost(xb[s], xbs[s]) - d_xb - cost(xn[4], xbs[s]) > 0) found = true;
-      if (d_p > d_xb && d_p + cost(xbp[s], xb[s]) - d_xb - cost(xn[2], xbp[s]) > 0) found = true;
+      if (s >= K) break;
+      const int d_xb = dxb[s];
+      if (d_s <= d_xb && d_p <= d_xb) break;
+      if (d_s > d_xb && d_s + cost(XB(s), XBS(s)) - d_xb - cost(XN(4), XBS(s)) > 0) return true;
+      if (d_p > d_xb && d_p + cost(XBP(s), XB(s)) - d_xb - cost(XN(2), XBP(s)) > 0) return true;
     }
   }
-  if (!found && (flags & LS_OROPT)) {
+  if (flags & LS_OROPT) {
     const int Lmax = or_lmax(I);
 #pragma unroll
     for (int vi = 0; vi < kOrSlots; ++vi) {
@@ -607,36 +721,42 @@ FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
       or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
       if (L > Lmax) continue;
       const int fpos = dir == 0 ? px : wrapn(px - L + 1, n);
-      const int2 xo = dir == 0 ? xn[ll] : xn[lf];
-      const int rem = dir == 0 ? cost(xn[lp], cx) : cost(cx, xn[lq]);
-      const int g_rem = cost(xn[lp], xn[lf]) + cost(xn[ll], xn[lq]) - cost(xn[lp], xn[lq]);
+      const int2 xo = dir == 0 ? XN(ll) : XN(lf);
+      const int rem = dir == 0 ? cost(XN(lp), cx) : cost(cx, XN(lq));
+      if (!(dxb[0] < rem)) continue;
+      const int g_rem = cost(XN(lp), XN(lf)) + cost(XN(ll), XN(lq)) - cost(XN(lp), XN(lq));
 #pragma unroll
       for (int s = 0; s < KT; ++s) {
-        if (s >= K) continue;
-        const int d_xb = cost(cx, xb[s]);
-        if (!(d_xb < rem)) continue;
+        if (s >= K) break;
+        const int d_xb = dxb[s];
+        if (!(d_xb < rem)) break;
         if (wrapn(pb[s] - fpos, n) < L) continue;
         const int pbs = pb[s] + 1 == n ? 0 : pb[s] + 1, pbp = pb[s] == 0 ? n - 1 : pb[s] - 1;
         if (wrapn(pbs - fpos, n) >= L &&
-            g_rem + cost(xb[s], xbs[s]) - d_xb - cost(xo, xbs[s]) > 0)
-          found = true;
+            g_rem + cost(XB(s), XBS(s)) - d_xb - cost(xo, XBS(s)) > 0)
+          return true;
         if (wrapn(pbp - fpos, n) >= L &&
-            g_rem + cost(xb[s], xbp[s]) - d_xb - cost(xo, xbp[s]) > 0)
-          found = true;
+            g_rem + cost(XB(s), XBP(s)) - d_xb - cost(xo, XBP(s)) > 0)
+          return true;
       }
     }
   }
-  return found;
+#undef XN
+#undef XB
+#undef XBS
+#undef XBP
+  return false;
 }
 
 constexpr int kChunks = 16;  // 64-element chunks in flight per round
 
 // Reverse the cyclic array range of length L starting at s (wave-wide).
-FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos) {
+FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos, int2 *rxy) {
   const int lane = lane_id();
   const int half = L >> 1;
   for (int base = 0; base < half; base += kChunks * kWave) {
     int p1[kChunks], p2[kChunks], v1[kChunks], v2[kChunks];
+    int c1x[kChunks], c1y[kChunks], c2x[kChunks], c2y[kChunks];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
       const int i = base + c * kWave + lane;
@@ -645,6 +765,9 @@ FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos) {
         p2[c] = wrap1(s + L - 1 - i, n);
         v1[c] = route[p1[c]];
         v2[c] = route[p2[c]];
+        const int2 a1 = rxy[p1[c]], a2 = rxy[p2[c]];
+        c1x[c] = a1.x; c1y[c] = a1.y;
+        c2x[c] = a2.x; c2y[c] = a2.y;
       }
     }
 #pragma unroll
@@ -653,6 +776,8 @@ FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos) {
       if (i < half) {
         route[p1[c]] = v2[c];
         route[p2[c]] = v1[c];
+        rxy[p1[c]] = make_int2(c2x[c], c2y[c]);
+        rxy[p2[c]] = make_int2(c1x[c], c1y[c]);
         pos[v2[c]] = p1[c];
         pos[v1[c]] = p2[c];
       }
@@ -663,14 +788,14 @@ FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos) {
 // "Flip a section between x and y": the shorter of the paths x..y and z..w.
 // px, py, pz: array positions of x, y, z.
 FACO_DEV int apply_2opt(int n, int px, int py, int pz, int32_t *route,
-                        int32_t *pos) {
+                        int32_t *pos, int2 *rxy) {
   const int L1 = wrapn(py - px, n) + 1;
   int moved;
   if (2 * L1 <= n) {
-    reverse_range(n, px, L1, route, pos);
+    reverse_range(n, px, L1, route, pos, rxy);
     moved = L1;
   } else {
-    reverse_range(n, pz, n - L1, route, pos);
+    reverse_range(n, pz, n - L1, route, pos, rxy);
     moved = n - L1;
   }
   wave_fence();
@@ -681,7 +806,8 @@ FACO_DEV int apply_2opt(int n, int px, int py, int pz, int32_t *route,
 // insertion edge exchange places (block keeps its orientation).
 FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
                          int pb, int fpos, int pq, int pp, int s0, int s1, int s2,
-                         int32_t *route, int32_t *pos) {
+                         int2 xs0, int2 xs1, int2 xs2, int32_t *route, int32_t *pos,
+                         int2 *rxy) {
   const int lane = lane_id();
   int x1, px1, px2;
   if (side == 0) {  // e = succ(b): edge (b, e)
@@ -697,21 +823,30 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
   int segv = s0;
   segv = lane == 1 ? s1 : segv;
   segv = lane == 2 ? s2 : segv;
+  int2 segx = xs0;
+  segx = lane == 1 ? xs1 : segx;
+  segx = lane == 2 ? xs2 : segx;
   const bool rev = (a != f) != (x1 != b);
   int src_lane = rev ? (L - 1 - lane) : lane;
   src_lane = src_lane < 0 ? 0 : (src_lane > 2 ? 2 : src_lane);
   const int ins = __shfl(segv, src_lane);
+  const int2 insx = shfl_i2(segx, src_lane);
   const int D1 = wrapn(px1 - pq, n) + 1;
   const int D2 = wrapn(pp - px2, n) + 1;
   int moved;
   if (D1 <= D2) {
     // block q..x1 moves back by L to start at fpos; segment follows it
     for (int base = 0; base < D1; base += kChunks * kWave) {
-      int v[kChunks];
+      int v[kChunks], cvx[kChunks], cvy[kChunks];
 #pragma unroll
       for (int c = 0; c < kChunks; ++c) {
         const int i = base + c * kWave + lane;
-        if (i < D1) v[c] = route[wrap1(pq + i, n)];
+        if (i < D1) {
+          const int sp = wrap1(pq + i, n);
+          v[c] = route[sp];
+          const int2 q = rxy[sp];
+          cvx[c] = q.x; cvy[c] = q.y;
+        }
       }
 #pragma unroll
       for (int c = 0; c < kChunks; ++c) {
@@ -719,6 +854,7 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
         if (i < D1) {
           const int d = wrap1(fpos + i, n);
           route[d] = v[c];
+          rxy[d] = make_int2(cvx[c], cvy[c]);
           pos[v[c]] = d;
         }
       }
@@ -726,6 +862,7 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
     if (lane < L) {
       const int d = wrapn(fpos + D1 + lane, n);
       route[d] = ins;
+      rxy[d] = insx;
       pos[ins] = d;
     }
     moved = D1 + L;
@@ -733,11 +870,16 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
     // block x2..p moves forward by L; segment goes in front of it
     const int top = ((D2 - 1) / (kChunks * kWave)) * (kChunks * kWave);
     for (int base = top; base >= 0; base -= kChunks * kWave) {
-      int v[kChunks];
+      int v[kChunks], cvx[kChunks], cvy[kChunks];
 #pragma unroll
       for (int c = 0; c < kChunks; ++c) {
         const int i = base + c * kWave + lane;
-        if (i < D2) v[c] = route[wrap1(px2 + i, n)];
+        if (i < D2) {
+          const int sp = wrap1(px2 + i, n);
+          v[c] = route[sp];
+          const int2 q = rxy[sp];
+          cvx[c] = q.x; cvy[c] = q.y;
+        }
       }
 #pragma unroll
       for (int c = 0; c < kChunks; ++c) {
@@ -745,6 +887,7 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
         if (i < D2) {
           const int d = wrapn(px2 + L + i, n);
           route[d] = v[c];
+          rxy[d] = make_int2(cvx[c], cvy[c]);
           pos[v[c]] = d;
         }
       }
@@ -752,6 +895,7 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
     if (lane < L) {
       const int d = wrap1(px2 + lane, n);
       route[d] = ins;
+      rxy[d] = insx;
       pos[ins] = d;
     }
     moved = D2 + L;
@@ -783,14 +927,14 @@ FACO_DEV void push(int n, int x, Queue &Q, int32_t *ring, uint32_t *inq,
 // Sweep: test every touched city (ascending id) and list the improvable ones.
 template <int KT>
 FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
-                   const int32_t *route, const int32_t *pos, int32_t *ring,
+                   const int32_t *route, const int32_t *pos, const int2 *rxy, int32_t *ring,
                    uint32_t *inq, uint32_t *touched) {
   const int lane = lane_id();
   int pushed = 0;
   int bx = -1, bcount = 0;
   auto flush = [&](int cnt) {
     bool f = false;
-    if (lane < cnt) f = has_improving<KT>(I, flags, bx, route, pos);
+    if (lane < cnt) f = has_improving<KT>(I, flags, bx, route, pos, rxy);
     uint64_t m = ballot(f);
     while (m) {
       const int l = ctz64(m);
@@ -822,11 +966,10 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
   return pushed;
 }
 
-FACO_DEV int64_t ticks() { return (int64_t)wall_clock64(); }
 
 template <int KT>
 FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
-                              int32_t *pos, int32_t *ring, uint32_t *inq,
+                              int32_t *pos, int2 *rxy, int32_t *ring, uint32_t *inq,
                               uint32_t *touched, int W, Queue Q, int64_t *cnt,
                               int64_t *tk) {
   constexpr int GS = KT <= 16 ? 16 : 32;  // lanes per evaluated city
@@ -851,9 +994,15 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
 #pragma unroll
       for (int g = 1; g < G; ++g) a = grp == g ? e[g] : a;
       const int64_t t0 = ticks();
-      const GroupEval R = eval_group<GS>(I, flags, a, grp < gcount, route, pos);
+      GroupEval R = eval_group<GS>(I, flags, a, grp < gcount, route, pos, rxy);
+      // Or-opt is only tried where no 2-opt move exists, and only cities
+      // before the first one with a 2-opt move can be the chosen one
+      const uint64_t h2 = ballot((lane & (GS - 1)) == 0 && grp < gcount && R.key2 > 0);
+      const int j2 = h2 ? ctz64(h2) / GS : gcount;
+      if ((flags & LS_OROPT) && j2 > 0) eval_group_oropt<GS>(I, grp < j2, R);
       const int64_t t1 = ticks();
       tk[1] += t1 - t0;
+      tk[12]++;
       const uint64_t hm = ballot((lane & (GS - 1)) == 0 && grp < gcount &&
                                  (R.key2 > 0 || R.keyo > 0));
       const int j = hm ? ctz64(hm) / GS : gcount;
@@ -870,7 +1019,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       if (j >= gcount) continue;
       const Move mv = extract_move<GS>(I, R, j);
       if (mv.kind == 1) {
-        cnt[CNT_MOVED_ELEMS] += apply_2opt(n, mv.px, mv.py, mv.pz, route, pos);
+        cnt[CNT_MOVED_ELEMS] += apply_2opt(n, mv.px, mv.py, mv.pz, route, pos, rxy);
         push(n, mv.w, Q, ring, inq, touched);
         push(n, mv.x, Q, ring, inq, touched);
         push(n, mv.y, Q, ring, inq, touched);
@@ -879,7 +1028,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       } else {
         cnt[CNT_MOVED_ELEMS] +=
             apply_oropt(n, mv.L, mv.a, mv.f, mv.b, mv.e, mv.side, mv.pb, mv.fpos, mv.pq,
-                        mv.pp, mv.s0, mv.s1, mv.s2, route, pos);
+                        mv.pp, mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2, route, pos, rxy);
         push(n, mv.p, Q, ring, inq, touched);
         push(n, mv.q, Q, ring, inq, touched);
         push(n, mv.b, Q, ring, inq, touched);
@@ -900,7 +1049,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     changes_at_sweep = changes;
     cnt[CNT_SWEEPS]++;
     const int64_t t2 = ticks();
-    const int pushed = sweep<KT>(I, flags, W, Q, route, pos, ring, inq, touched);
+    const int pushed = sweep<KT>(I, flags, W, Q, route, pos, rxy, ring, inq, touched);
     tk[3] += ticks() - t2;
     if (pushed == 0) break;
   }
@@ -922,15 +1071,18 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   int32_t *route = I.routes + (size_t)ant * (size_t)n;
   int32_t *pos = I.pos + (size_t)ant * (size_t)n;
   int32_t *ring = I.ring + (size_t)ant * (size_t)n;
+  int2 *rxy = I.rxy + (size_t)ant * (size_t)n;
   int64_t cnt[NCNT];
 #pragma unroll
   for (int c = 0; c < NCNT; ++c) cnt[c] = 0;
-  int64_t tk[4] = {0, 0, 0, 0};
+  int64_t tk[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) tk[c] = 0;
   const bool init = mode == 1;
   const uint64_t t = (uint64_t)I.st->iter + 1;
   int nchk = 0;
   const int64_t t0 = ticks();
-  int64_t len = construct<KT>(I, t, ant, init, route, pos, ring, vis, inq, W, nchk, cnt);
+  int64_t len = construct<KT>(I, t, ant, init, route, pos, rxy, ring, vis, inq, W, nchk, cnt, tk);
   tk[0] = ticks() - t0;
   uint32_t flags = I.ls_flags;
   Queue Q;
@@ -961,7 +1113,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   }
   wave_fence();
   if (flags & (LS_2OPT | LS_OROPT))
-    len -= local_search<KT>(I, flags, route, pos, ring, inq, vis, W, Q, cnt, tk);
+    len -= local_search<KT>(I, flags, route, pos, rxy, ring, inq, vis, W, Q, cnt, tk);
   if (init) {
     for (int i = lane; i < n; i += kWave) I.gb_route[i] = route[i];
     if (lane == 0) {
@@ -977,12 +1129,10 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
       I.cnt[(size_t)ant * NCNT + c] = cnt[c];
       I.cnt_acc[(size_t)ant * NCNT + c] += cnt[c];
     }
-    int64_t *tr = I.ticks + (size_t)ant * 8;
-    tr[0] += tk[0];
-    tr[1] += tk[1];
-    tr[2] += tk[2];
-    tr[3] += tk[3];
-    tr[4] += ticks() - t0;
+    int64_t *tr = I.ticks + (size_t)ant * 16;
+    tk[4] = ticks() - t0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) tr[c] += tk[c];
   }
 }
 
@@ -1095,9 +1245,14 @@ FACO_DEV void run_pheromone(const Inst &I, size_t idx, int init) {
     tnew = t2;
   }
   I.tau[idx] = tnew;
-  // tables read by the next construction: Eq. (1) weight and source position
-  I.w[idx] = tnew * I.eta[idx];
-  I.cl_spos[idx] = I.src_pos[j];
+  // candidate row of city i moved to row src_pos(i), read by the next
+  // construction: the city, its Eq. (1) weight, source position and cost
+  const int i = (int)(idx / (size_t)K), s = (int)(idx - (size_t)i * K);
+  const size_t o = (size_t)I.src_pos[i] * (size_t)K + s;
+  I.scl[o] = j;
+  I.sw[o] = tnew * I.eta[idx];
+  I.ssp[o] = I.src_pos[j];
+  I.sd[o] = I.cl_d[idx];
 }
 
 __global__ void __launch_bounds__(256) pheromone_kernel(Inst I, int init) {

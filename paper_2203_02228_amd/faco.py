@@ -206,7 +206,7 @@ def faco_debug_get(inst, what):
         FACO_DBG_INFO: (np.int64, (8,)),
         FACO_DBG_INIT_COUNTERS: (np.int64, (FACO_NCNT,)),
         FACO_DBG_COUNTER_TOTALS: (np.int64, (A, FACO_NCNT)),
-        FACO_DBG_PHASE_TICKS: (np.int64, (A, 8)),
+        FACO_DBG_PHASE_TICKS: (np.int64, (A, 16)),
     }
     dt, shape = shapes[what]
     out = np.zeros(shape, dtype=dt)

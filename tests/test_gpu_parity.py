@@ -131,3 +131,23 @@ def test_build_errors():
     with pytest.raises(F.FacoError) as e:
         F.faco_build_instance(xy, rho=1.5)
     assert e.value.code == F.FACO_EINVAL
+
+
+def test_full_coordinate_range():
+    """Coordinates up to 2^23 - 1 (squared lengths up to 2^47): the cost
+    function's extreme range, including near-collinear and far pairs."""
+    rng = np.random.default_rng(77)
+    pts = rng.integers(0, (1 << 23), size=(1500, 2))
+    pts[:20, 0] = (1 << 23) - 1 - np.arange(20)       # a column at the far edge
+    pts[20:40] = np.stack([np.arange(20) * 3, np.zeros(20, np.int64)], 1)  # tight row
+    xy = np.unique(pts, axis=0).astype(np.int32)
+    xy = xy[rng.permutation(len(xy))]
+    params = dict(n_ants=8, min_new_edges=6, rho=0.5)
+    say(f"[gpu] full coordinate range n={len(xy)}")
+    o, g = _pair(xy, **params)
+    _cmp_setup(o, g)
+    for it in range(1, 6):
+        o.run(1)
+        F.faco_run_iterations(g, 1)
+        _cmp_iter(o, g, it)
+    g.close()
