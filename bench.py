@@ -22,6 +22,35 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def kernel_source_hash():
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_02228_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload, warmup, steps):
+    """HBM bytes per ant-kernel launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on this kernel source over this window."""
+    path = os.path.join(ROOT, "profiles", f"ant_kernel_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("#", "|", "`", "cd ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    if kv.get("window") != f"{warmup + 1}..{warmup + steps}":
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def algorithmic_bytes_per_ant(cnt, n, k, bl):
     """Bytes the array-based ant must move, from its counters (per ant-tour):
     ACO step: candidate, pheromone and heuristic rows (12k) + source
@@ -201,8 +230,10 @@ def run_served_mode(args, quick=False):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    # default: the whole configured run of the workload (1000 iterations from
+    # the built instance)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="stipple100k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -326,7 +357,8 @@ def main():
                                                              "pheromone"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": None, "kernel": "ant_kernel",
+                     "traffic": profiled_traffic(w.name, args.warmup, args.steps),
+                     "kernel": "ant_kernel",
                      "avg_launch_ms": round(ant_ms, 4)},
     }
     if not args.no_cpu_baseline:
