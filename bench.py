@@ -245,6 +245,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB for resident solves")
     ap.add_argument("--seq-sample", type=int, default=16)
+    ap.add_argument("--team-waves", type=int, default=0,
+                    help="waves per ant (0 = the library's choice by size; 1, 4, 8)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied once by a plain device-to-device copy kernel before "
                          "the workload (scales hardware byte counters)")
@@ -284,9 +286,11 @@ def main():
               file=sys.stderr, flush=True)
         del src, dst
     stream = torch.cuda.current_stream()
+    F.faco_set_team_waves(args.team_waves)
     t0 = time.time()
     g = F.faco_build_instance(xy, stream=stream, **params)
     build_s = time.time() - t0
+    team_waves = int(F.faco_debug_get(g, F.FACO_DBG_TEAM_WAVES)[0])
     print(f"[bench] built {w.name} n={w.n} in {build_s:.2f} s", file=sys.stderr, flush=True)
     F.faco_run_iterations(g, args.warmup)
     torch.cuda.synchronize()
@@ -347,7 +351,8 @@ def main():
                    "cl_size": k, "bl_size": bl, "rho": w.rho, "p_best": 0.05,
                    "local_search": "2-opt+Or-opt+sweep", "iterations_timed":
                    f"{args.warmup + 1}..{args.warmup + args.steps}",
-                   "best_length": int(best_len), "iterations_done": int(info[0])},
+                   "best_length": int(best_len), "iterations_done": int(info[0]),
+                   "waves_per_ant": team_waves, "build_s": round(build_s, 2)},
         "per_ant_us": tk_us,
         "per_ant_calls": tk_calls,
         "slowest_ant_us": slowest_us,

@@ -122,6 +122,15 @@ int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
  * Errors: FACO_EINVAL. */
 int faco_set_batch_ants_per_block(int32_t ants_per_block);
 
+/* Waves per ant in the per-instance ant kernel, for instances built after
+ * the call (process-wide): 1, 4 or 8, or 0 for a choice by size (1 below
+ * 2048 cities; else 8 up to 256 ants, 4 up to 512, 1 beyond).  Wave 0 of an
+ * ant makes every decision; the others share its wide steps (speculative
+ * source-following windows of 64 steps per wave, the array rewrites of 2-opt
+ * and Or-opt moves, sweep tests).  An execution-shape choice that never
+ * changes results.  Errors: FACO_EINVAL. */
+int faco_set_team_waves(int32_t team_waves);
+
 /* Debug / test dumps of the state after the last completed iteration.  Sync,
  * then copy `bytes` bytes into the host buffer `out`; `bytes` must equal the
  * size given below, otherwise FACO_EINVAL. */
@@ -141,7 +150,7 @@ enum {
   FACO_DBG_INIT_COUNTERS = 10, /* int64 [FACO_NCNT] of the initial solution  */
   FACO_DBG_COUNTER_TOTALS = 11, /* int64 [n_ants][FACO_NCNT], summed over all
                                    iterations since the build                 */
-  FACO_DBG_PHASE_TICKS = 12 /* int64 [n_ants][16] summed since the build;
+  FACO_DBG_PHASE_TICKS = 12, /* int64 [n_ants][16] summed since the build;
                                device wall-clock ticks (100 MHz): [0]
                                construction, [1] move evaluation, [2] move
                                application, [3] sweeps, [4] whole ant, [8]
@@ -149,6 +158,7 @@ enum {
                                [10] copies, [11] backup/nearest choices; call
                                counts: [5] windows, [6] one-step choices, [7]
                                copies, [12] evaluation rounds             */
+  FACO_DBG_TEAM_WAVES = 13  /* int32 [1]: waves per ant of this instance   */
 };
 /* per-ant counters (same meaning as the oracle's) */
 enum {

@@ -1,16 +1,20 @@
-"""Build step of the HIP library: compiles csrc/faco_api.hip for gfx950 into
-libfaco_hip.so beside this file."""
+"""Build step of the HIP library: compiles the sources under csrc/ for gfx950
+(the ant kernels of each team size in a translation unit of their own, in
+parallel) and links libfaco_hip.so beside this file."""
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "faco_api.hip")
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = ["faco_api.hip", "ant_tw1.hip", "ant_tw4.hip", "ant_tw8.hip"]
 OUT = os.path.join(HERE, "libfaco_hip.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # bit-exact binary32/binary64 arithmetic: no contraction into FMA
     "-ffp-contract=off",
     # no packed fp32 instructions
@@ -19,8 +23,20 @@ FLAGS = [
 ]
 
 
+def _compile(src, verbose):
+    obj = os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
 def build(verbose=False):
-    cmd = [HIPCC, *FLAGS, SRC, "-o", OUT + ".tmp"]
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

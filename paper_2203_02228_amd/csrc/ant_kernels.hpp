@@ -1,0 +1,17 @@
+// ant_kernels.hpp -- host-side access to the ant kernels, which are compiled
+// in their own translation units (one per team size).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "faco_device.hpp"
+
+typedef void (*AntKernelFn)(faco::Inst, int);
+typedef void (*AntBatchFn)(const faco::Inst *, const int2 *, int, int, int);
+
+// ant kernel for candidate lists of length k (specialised for KT >= k) with
+// tw waves per ant (1, 4 or 8); nullptr for another tw
+AntKernelFn faco_ant_kernel(int k, int tw);
+// batched ant kernel (one wave per ant)
+AntBatchFn faco_ant_batch_kernel(int k);
+// LDS words of the team area ahead of an ant's bitmaps
+int faco_team_lds_words(int tw);

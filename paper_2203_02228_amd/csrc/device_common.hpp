@@ -67,6 +67,19 @@ FACO_DEV int wave_min_i32(int v) {
   return v;
 }
 
+// A value every lane holds alike, moved to a scalar register: control flow
+// on it is a scalar branch (needed where a workgroup barrier follows).
+FACO_DEV int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+FACO_DEV uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Workgroup barrier; global and LDS writes before it are visible to every
+// wave of the workgroup after it.
+FACO_DEV void team_sync() { __syncthreads(); }
+
 // Make this wave's global and LDS writes visible to its other lanes.
 FACO_DEV void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

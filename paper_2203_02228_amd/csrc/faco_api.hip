@@ -1,7 +1,7 @@
 // faco_api.hip -- host side of the C ABI declared in include/faco.h.
 //
 // Owns the device state of each instance, validates arguments, launches the
-// kernels of faco_kernels.hpp on the instance's stream.  No step of the
+// kernels on the instance's stream.  No step of the
 // method runs on the host: the host only derives p_best^(1/n) once per build
 // (a parameter of the trail-limit formula, Sec. 4.5) and marshals pointers.
 #include <hip/hip_runtime.h>
@@ -15,7 +15,8 @@
 #include <vector>
 
 #include "../../include/faco.h"
-#include "faco_kernels.hpp"
+#include "ant_kernels.hpp"
+#include "faco_aux.hpp"
 
 using faco::DevState;
 using faco::Inst;
@@ -33,6 +34,7 @@ struct faco_instance {
   std::vector<void *> allocs;
   std::string err;
   size_t lds_ant = 0;
+  int tw = 1;  // waves per ant in the per-instance ant kernel
   bool timing = false;
   std::vector<TimedLaunch> pending;
   double phase_ms[4] = {0, 0, 0, 0};
@@ -89,7 +91,9 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   const uint64_t N = (uint64_t)n, A = (uint64_t)p->n_ants;
   uint64_t b = 0;
   b += align_up(8 * N);                    // xy
-  b += 8 * align_up(4 * N * (uint64_t)k);  // cl, cost, eta, tau + source-ordered rows (city, weight, position, cost)
+  const uint64_t NB = (N + 63) / 64 * 64;   // source-ordered tables: whole 64-position blocks
+  b += 4 * align_up(4 * N * (uint64_t)k);   // cl, cost, eta, tau
+  b += 4 * align_up(4 * NB * (uint64_t)k);  // source-ordered city, weight, position, cost
   b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
   b += 4 * align_up(4 * N) + align_up(8 * N); // source route/pos/edge costs, adjacency, global best
   b += 3 * align_up(4 * N * A) + align_up(8 * N * A);  // ant routes, pos, rings, tour coordinates
@@ -123,15 +127,30 @@ static void end_timed(faco_instance *h, TimedLaunch &tl) {
   h->pending.push_back(tl);
 }
 
-// ant kernel specialised for the candidate-list length (KT >= k)
-typedef void (*AntKernelFn)(Inst, int);
-static AntKernelFn ant_kernel_for(int k) {
-  if (k <= 4) return faco::ant_kernel<4>;
-  if (k <= 8) return faco::ant_kernel<8>;
-  if (k <= 12) return faco::ant_kernel<12>;
-  if (k <= 16) return faco::ant_kernel<16>;
-  if (k <= 24) return faco::ant_kernel<24>;
-  return faco::ant_kernel<32>;
+// Waves per ant for instances built from now on (0 = by size: large tours
+// with few enough ants to leave the chip's wave slots to the teams).
+static std::mutex g_team_mu;
+static int g_team_waves = 0;
+
+extern "C" int faco_set_team_waves(int32_t tw) {
+  if (tw != 0 && tw != 1 && tw != 4 && tw != 8)
+    return set_err(nullptr, FACO_EINVAL, "team waves must be 0, 1, 4 or 8");
+  std::lock_guard<std::mutex> lk(g_team_mu);
+  g_team_waves = tw;
+  return FACO_OK;
+}
+
+static int team_waves_for(int32_t n, int32_t ants) {
+  int tw;
+  {
+    std::lock_guard<std::mutex> lk(g_team_mu);
+    tw = g_team_waves;
+  }
+  if (tw) return tw;
+  if (n < 2048) return 1;
+  if (ants <= 256) return 8;
+  if (ants <= 512) return 4;
+  return 1;
 }
 
 // enqueue the four phases of one iteration
@@ -143,7 +162,8 @@ static int enqueue_iteration(faco_instance *h) {
   const unsigned nb_tau = (unsigned)((slots + 255) / 256);
   TimedLaunch tl;
   if (h->timing) begin_timed(h, 0, tl);
-  hipLaunchKernelGGL(ant_kernel_for(h->k), dim3(h->p.n_ants), dim3(64), h->lds_ant, h->stream, I, 0);
+  hipLaunchKernelGGL(faco_ant_kernel(h->k, h->tw), dim3(h->p.n_ants), dim3(64 * h->tw),
+                     h->lds_ant, h->stream, I, 0);
   if (h->timing) {
     end_timed(h, tl);
     begin_timed(h, 1, tl);
@@ -180,6 +200,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   effective_sizes(n, p, &h->k, &h->bl);
   h->stream = (hipStream_t)hip_stream;
   const size_t N = (size_t)n, A = (size_t)p->n_ants, K = (size_t)h->k, BL = (size_t)h->bl;
+  const size_t NB = (N + 63) / 64 * 64;
 
   Inst &I = h->dv;
   I.n = n;
@@ -209,10 +230,10 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   ALLOC(eta, float, N * K);
   ALLOC(cl_d, int32_t, N * K);
   ALLOC(tau, float, N * K);
-  ALLOC(scl, int32_t, N * K);
-  ALLOC(sw, float, N * K);
-  ALLOC(ssp, int32_t, N * K);
-  ALLOC(sd, int32_t, N * K);
+  ALLOC(scl, int32_t, NB * K);
+  ALLOC(sw, float, NB * K);
+  ALLOC(ssp, int32_t, NB * K);
+  ALLOC(sd, int32_t, NB * K);
   ALLOC(src_route, int32_t, N);
   ALLOC(src_pos, int32_t, N);
   ALLOC(gb_route, int32_t, N);
@@ -261,11 +282,14 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
     return fail(FACO_EDUP);
   }
 
-  h->lds_ant = sizeof(uint32_t) * 2 * (size_t)((n + 31) / 32);
-  BTRY(hipFuncSetAttribute((const void *)ant_kernel_for(h->k),
+  h->tw = team_waves_for(n, p->n_ants);
+  h->lds_ant = sizeof(uint32_t) * ((size_t)faco_team_lds_words(h->tw) +
+                                   2 * (size_t)((n + 31) / 32));
+  BTRY(hipFuncSetAttribute((const void *)faco_ant_kernel(h->k, h->tw),
                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_ant));
   // initial solution (ant slot 0), limits, tau = tau_max, source = global best
-  hipLaunchKernelGGL(ant_kernel_for(h->k), dim3(1), dim3(64), h->lds_ant, h->stream, I, 1);
+  hipLaunchKernelGGL(faco_ant_kernel(h->k, h->tw), dim3(1), dim3(64 * h->tw), h->lds_ant,
+                     h->stream, I, 1);
   hipLaunchKernelGGL(faco::init_state_kernel, dim3(1), dim3(1), 0, h->stream, I);
   hipLaunchKernelGGL(faco::source_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      h->stream, I, 1);
@@ -350,6 +374,12 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
       std::memcpy(out, v, 64);
       return FACO_OK;
     }
+    case FACO_DBG_TEAM_WAVES: {
+      if (bytes != 4) return set_err(h, FACO_EINVAL, "size mismatch");
+      const int32_t tw = h->tw;
+      std::memcpy(out, &tw, 4);
+      return FACO_OK;
+    }
     case FACO_DBG_INIT_COUNTERS: {
       if (bytes != 8 * faco::NCNT) return set_err(h, FACO_EINVAL, "size mismatch");
       std::memcpy(out, hs.init_cnt, 8 * faco::NCNT);
@@ -393,15 +423,6 @@ extern "C" int faco_phase_times(faco_instance *h, double *ms_out, int64_t *launc
 // Batched execution (faco_run_batch).  The launch tables live in a
 // process-wide workspace that grows on demand; calls are serialised.
 
-typedef void (*AntBatchFn)(const Inst *, const int2 *, int, int, int);
-static AntBatchFn ant_batch_for(int k) {
-  if (k <= 4) return faco::ant_batch_kernel<4>;
-  if (k <= 8) return faco::ant_batch_kernel<8>;
-  if (k <= 12) return faco::ant_batch_kernel<12>;
-  if (k <= 16) return faco::ant_batch_kernel<16>;
-  if (k <= 24) return faco::ant_batch_kernel<24>;
-  return faco::ant_batch_kernel<32>;
-}
 
 static std::mutex g_batch_mu;
 static int g_batch_apb = 1;  // ants (waves) per workgroup in batched launches
@@ -488,7 +509,7 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
                     hipMemcpyHostToDevice, st));
   BT(hipMemcpyAsync(g_ws.amap, amap.data(), sizeof(int2) * (size_t)total,
                     hipMemcpyHostToDevice, st));
-  AntBatchFn antk = ant_batch_for(kmax);
+  AntBatchFn antk = faco_ant_batch_kernel(kmax);
   BT(hipFuncSetAttribute((const void *)antk, hipFuncAttributeMaxDynamicSharedMemorySize,
                          (int)lds_bytes));
   const unsigned nb_ant = (unsigned)((total + apb - 1) / apb);

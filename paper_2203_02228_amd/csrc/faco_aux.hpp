@@ -1,0 +1,217 @@
+// faco_aux.hpp -- per-iteration colony, source and pheromone kernels, the
+// batched forms of those, and the candidate/backup list builder (gfx950).
+#pragma once
+#include "device_common.hpp"
+#include "faco_device.hpp"
+
+namespace faco {
+
+// ===================================================================== //
+// Colony update (after the ants): iteration best, global best + limits
+// (Sec. 4.5), source choice.  One wave.
+// ===================================================================== //
+FACO_DEV void limits(const Inst &I, int64_t gb_len, float &tmin_f, float &tmax_f) {
+  const double tmax = 1.0 / ((double)gb_len * (1.0 - (double)I.rho));
+  const double num = 1.0 - I.p_root;
+  const double den = (double)(I.k - 1) * I.p_root;
+  double tmin = tmax * num / den;
+  if (tmin > tmax) tmin = tmax;
+  tmax_f = (float)tmax;
+  tmin_f = (float)tmin;
+}
+
+FACO_DEV void run_colony(const Inst &I) {
+  const int lane = lane_id();
+  DevState *st = I.st;
+  const uint64_t t = (uint64_t)st->iter + 1;
+  int64_t bl = INT64_MAX;
+  int ba = 0x7fffffff;
+  for (int a = lane; a < I.A; a += kWave) {
+    const int64_t L = I.lens[a];
+    if (L < bl) {
+      bl = L;
+      ba = a;
+    }
+  }
+  const int64_t minL = wave_min_i64(bl);
+  const int ib = wave_min_i32(bl == minL ? ba : 0x7fffffff);
+  int64_t gb = st->gb_len;
+  const bool improved = minL < gb;
+  float tmin = st->tau_min, tmax = st->tau_max;
+  if (improved) {
+    gb = minL;
+    limits(I, gb, tmin, tmax);
+  }
+  const uint64_t x = philox_word0(I.seed, t, ~0ull, 0, kPurposeSource);
+  const bool use_gb = (double)(uint32_t)(x >> 40) < I.p_gb * 16777216.0;
+  const int64_t src_len = use_gb ? gb : minL;
+  const float delta = (float)(1.0 / (double)src_len);
+  if (lane == 0) {
+    st->gb_len = gb;
+    st->tau_min = tmin;
+    st->tau_max = tmax;
+    st->ib = ib;
+    st->improved = improved ? 1 : 0;
+    st->src_gb = use_gb ? 1 : 0;
+    st->src_len = src_len;
+    st->delta = delta;
+    st->iter = (int64_t)t;
+  }
+}
+
+__global__ void __launch_bounds__(64) colony_kernel(Inst I) { run_colony(I); }
+
+// Source materialisation: the chosen tour becomes source_solution (route and
+// its inverse), the iteration best becomes the global best when it improved.
+// init: source := global best (before the first iteration).
+FACO_DEV void run_source(const Inst &I, int i, int init) {
+  const int n = I.n;
+  if (i >= n) return;
+  const DevState *st = I.st;
+  const int i1 = i + 1 == n ? 0 : i + 1, i0 = i == 0 ? n - 1 : i - 1;
+  const int32_t *from;
+  if (init) {
+    from = I.gb_route;
+  } else {
+    const int32_t *ibr = I.routes + (size_t)st->ib * (size_t)n;
+    from = (st->src_gb && !st->improved) ? I.gb_route : ibr;
+  }
+  const int node = from[i], next = from[i1], prev = from[i0];
+  if (!init && st->improved) I.gb_route[i] = node;
+  I.src_route[i] = node;
+  I.src_pos[node] = i;
+  I.src_adj[node] = make_int2(next, prev);
+  I.src_d[i] = cost(I.xy[node], I.xy[next]);
+}
+
+__global__ void __launch_bounds__(256) source_kernel(Inst I, int init) {
+  run_source(I, (int)(blockIdx.x * blockDim.x + threadIdx.x), init);
+}
+
+// Eq. (2) with the deposit on the source edges: tau' = clamp(rho tau + delta
+// [edge in source]).  init: tau = tau_max everywhere.
+FACO_DEV void run_pheromone(const Inst &I, size_t idx, int init) {
+  const int n = I.n, K = I.k;
+  if (idx >= (size_t)n * (size_t)K) return;
+  const DevState *st = I.st;
+  const float tmin = st->tau_min, tmax = st->tau_max;
+  const int j = I.cl[idx];
+  float tnew;
+  if (init) {
+    tnew = tmax;
+  } else {
+    const int i = (int)(idx / (size_t)K);
+    const int2 adj = I.src_adj[i];
+    const float t1 = I.rho * I.tau[idx];
+    float t2 = (j == adj.x || j == adj.y) ? t1 + st->delta : t1;
+    if (t2 > tmax) t2 = tmax;
+    if (t2 < tmin) t2 = tmin;
+    tnew = t2;
+  }
+  I.tau[idx] = tnew;
+  // candidate row of city i moved to row src_pos(i), read by the next
+  // construction: the city, its Eq. (1) weight, source position and cost
+  const int i = (int)(idx / (size_t)K), s = (int)(idx - (size_t)i * K);
+  const size_t o = srow(I.src_pos[i], s, K);
+  I.scl[o] = j;
+  I.sw[o] = tnew * I.eta[idx];
+  I.ssp[o] = I.src_pos[j];
+  I.sd[o] = I.cl_d[idx];
+}
+
+__global__ void __launch_bounds__(256) pheromone_kernel(Inst I, int init) {
+  run_pheromone(I, (size_t)blockIdx.x * blockDim.x + threadIdx.x, init);
+}
+
+// Limits of the initial solution; state before the first iteration.
+__global__ void init_state_kernel(Inst I) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  DevState *st = I.st;
+  float tmin, tmax;
+  limits(I, st->gb_len, tmin, tmax);
+  st->tau_min = tmin;
+  st->tau_max = tmax;
+  st->src_len = st->gb_len;
+  st->delta = 0.0f;
+  st->ib = -1;
+  st->src_gb = 0;
+  st->improved = 0;
+  st->iter = 0;
+}
+
+
+// ===================================================================== //
+// Batched forms: blockIdx selects the instance; each instance reads only
+// its own Inst.
+// ===================================================================== //
+__global__ void __launch_bounds__(64) colony_batch_kernel(const Inst *insts) {
+  run_colony(insts[blockIdx.x]);
+}
+
+// blockIdx.y = instance; blocks past an instance's size return
+__global__ void __launch_bounds__(256) source_batch_kernel(const Inst *insts) {
+  run_source(insts[blockIdx.y], (int)(blockIdx.x * blockDim.x + threadIdx.x), 0);
+}
+
+__global__ void __launch_bounds__(256) pheromone_batch_kernel(const Inst *insts) {
+  run_pheromone(insts[blockIdx.y], (size_t)blockIdx.x * blockDim.x + threadIdx.x, 0);
+}
+
+// ===================================================================== //
+// Candidate + backup lists (Sec. 4.1): the K + BL nearest cities by
+// (squared distance, id); eta = 1/d.  One query city per lane; candidate
+// cities stream through LDS in tiles; each lane keeps its sorted list in LDS.
+// ===================================================================== //
+constexpr int kKnnTile = 256;
+
+__global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, int n, int K, int BL,
+                                                 int32_t *cl, int32_t *bll, float *eta,
+                                                 int32_t *cl_d, DevState *st) {
+  extern __shared__ unsigned char knn_lds[];
+  const int KK = K + BL;
+  const int tid = threadIdx.x;
+  int2 *tile = reinterpret_cast<int2 *>(knn_lds);
+  double *kd = reinterpret_cast<double *>(knn_lds + sizeof(int2) * kKnnTile);
+  int32_t *kj = reinterpret_cast<int32_t *>(knn_lds + sizeof(int2) * kKnnTile +
+                                            sizeof(double) * (size_t)KK * 64);
+  const int i = blockIdx.x * 64 + tid;
+  const bool valid = i < n;
+  const int2 xi = valid ? xy[i] : make_int2(0, 0);
+  int cnt = 0;
+  double worst = 0.0;
+  for (int t0 = 0; t0 < n; t0 += kKnnTile) {
+    __syncthreads();
+    for (int j = tid; j < kKnnTile; j += 64)
+      if (t0 + j < n) tile[j] = xy[t0 + j];
+    __syncthreads();
+    const int tn = min(kKnnTile, n - t0);
+    if (!valid) continue;
+    for (int jj = 0; jj < tn; ++jj) {
+      const int j = t0 + jj;
+      if (j == i) continue;
+      const double d = sqd(xi, tile[jj]);
+      if (cnt == KK && !(d < worst)) continue;
+      int q = cnt < KK ? cnt++ : KK - 1;
+      while (q > 0 && kd[(q - 1) * 64 + tid] > d) {
+        kd[q * 64 + tid] = kd[(q - 1) * 64 + tid];
+        kj[q * 64 + tid] = kj[(q - 1) * 64 + tid];
+        --q;
+      }
+      kd[q * 64 + tid] = d;
+      kj[q * 64 + tid] = j;
+      if (cnt == KK) worst = kd[(KK - 1) * 64 + tid];
+    }
+  }
+  if (!valid) return;
+  for (int s = 0; s < K; ++s) {
+    const double d2 = kd[s * 64 + tid];
+    cl[(size_t)i * K + s] = kj[s * 64 + tid];
+    const int d = (int)floor(sqrt(d2) + 0.5);
+    cl_d[(size_t)i * K + s] = d;
+    eta[(size_t)i * K + s] = (float)(1.0 / (double)d);
+  }
+  for (int s = 0; s < BL; ++s) bll[(size_t)i * BL + s] = kj[(K + s) * 64 + tid];
+  if (kd[tid] == 0.0) atomicOr(&st->dup, 1);
+}
+
+}  // namespace faco

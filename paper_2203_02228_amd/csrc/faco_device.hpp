@@ -45,11 +45,12 @@ struct Inst {
   int32_t *src_route, *src_pos, *gb_route;
   int2 *src_adj;      // [n] (successor, predecessor) of each city in the source
   // Candidate rows in SOURCE order (row p = candidates of the city at source
-  // position p), rewritten by the pheromone kernel every iteration:
-  int32_t *scl;       // [n][k] candidate city
-  float *sw;          // [n][k] tau * eta (Eq. (1) weight)
-  int32_t *ssp;       // [n][k] source position of the candidate
-  int32_t *sd;        // [n][k] cost of the candidate edge
+  // position p), rewritten by the pheromone kernel every iteration; laid out
+  // by srow() in blocks of 64 positions:
+  int32_t *scl;       // candidate city
+  float *sw;          // tau * eta (Eq. (1) weight)
+  int32_t *ssp;       // source position of the candidate
+  int32_t *sd;        // cost of the candidate edge
   int32_t *src_d;     // [n] cost of the source edge from position i to i + 1
   int32_t *routes, *pos, *ring;
   int2 *rxy;          // [A][n] coordinates of routes[a][p] (tour order)
@@ -78,5 +79,13 @@ constexpr uint32_t LS_2OPT = 1u, LS_OROPT = 2u, LS_SWEEP = 4u;
 constexpr int kMaxCl = 32;
 constexpr int kMaxBl = 64;
 constexpr int kMaxOrSeg = 3;
+
+// Element (position p, slot s) of a source-ordered table with k slots: 64
+// consecutive positions form a block, slot-major inside it, so the lanes of
+// a window (consecutive positions, one slot per load) read adjacent words.
+// A table holds ceil(n / 64) * 64 * k elements.
+__device__ __forceinline__ size_t srow(int p, int s, int k) {
+  return ((size_t)(p >> 6) * (size_t)k + (size_t)s) * 64u + (size_t)(p & 63);
+}
 
 }  // namespace faco

@@ -30,14 +30,56 @@ FACO_DEV int wrapn(int q, int n) {
 // for 0 <= q < 2n
 FACO_DEV int wrap1(int q, int n) { return q >= n ? q - n : q; }
 
-// Offset a source position by |off| <= 256 (cheap form when n > 256).
+// Offset a source position by |off| <= 4096 (cheap form when n >= 4096).
 FACO_DEV int wrap_off(int q, int off, int n) {
-  if (n > 256) {
+  if (n >= 4096) {
     q += off;
     return q >= n ? q - n : (q < 0 ? q + n : q);
   }
   return wrapn(q + off, n);
 }
+
+// ===================================================================== //
+// Ant teams.  An ant may own TW waves of one workgroup.  Wave 0 (the leader)
+// runs every decision of the ant; the other waves wait at a workgroup
+// barrier for a command posted in LDS and take a share of the wide steps:
+// the speculative source-following window (64 TW steps at once), the array
+// rewrites of 2-opt and Or-opt moves, and the move tests of a sweep.  Who
+// computes a step never changes its result.
+//   protocol: leader writes op + arguments, barrier; every wave does its
+//   share (a step with a read/write hazard has barriers of its own, taken by
+//   every wave alike); barrier; the leader reads what the op left in LDS.
+// ===================================================================== //
+constexpr int kMaxTeam = 8;
+enum TeamOp { OP_EXIT = 0, OP_REVERSE = 1, OP_SHIFT = 2, OP_WINDOW = 3, OP_SWEEP = 4 };
+struct TeamLds {
+  int op;
+  int arg[11];
+  uint64_t arg64[2];
+  int f[kMaxTeam];               // window: first step that left the source, per wave
+  int res[4];                    // window: last followed city; decision v, dv, pv
+  int64_t part[kMaxTeam];        // window: per-wave sums of source edge costs
+  uint64_t mask[kMaxTeam];       // sweep: per-wave ballots
+  int cities[kMaxTeam * kWave];  // sweep: cities to test, in order
+};
+template <int TW>
+constexpr int team_words() {
+  return TW > 1 ? (int)((sizeof(TeamLds) + 15) / 16) * 4 : 0;
+}
+
+FACO_DEV void team_post(TeamLds *tl, int op, int a0 = 0, int a1 = 0, int a2 = 0, int a3 = 0,
+                        int a4 = 0) {
+  if (lane_id() == 0) {
+    tl->op = op;
+    tl->arg[0] = a0;
+    tl->arg[1] = a1;
+    tl->arg[2] = a2;
+    tl->arg[3] = a3;
+    tl->arg[4] = a4;
+  }
+  team_sync();
+}
+FACO_DEV int team_arg(const TeamLds *tl, int i) { return uniform_i(tl->arg[i]); }
 
 // ===================================================================== //
 // Backup list, then the nearest unvisited city (when no candidate of u is
@@ -198,39 +240,49 @@ struct Draws {
   bool valid;
 };
 
-template <int KT>
-FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
-                        int u, int pu, int dir, int k, int maxw, const uint32_t *vis,
-                        Draws &D, int &v, int &dv, int &pv, int &lastq,
-                        int64_t &src_len_sum) {
+struct WinOut {
+  int acc;        // steps that followed the source
+  int v, dv, pv;  // decision of step `step + acc` (v = -2: window ran out)
+  int lastq;      // city reached after the accepted steps
+  int64_t srcsum; // their edge costs
+};
+
+// Wave w of a team evaluates steps step + 64 w + lane (TW = 1: lanes only).
+// The accepted steps are appended to the tour here (route, pos, rxy and the
+// visited bits), by the wave that evaluated them.
+template <int KT, int TW>
+FACO_DEV void window_part(const Inst &I, uint64_t t, uint64_t ant, uint64_t step, int u,
+                          int pu, int dir, int k, int maxw, int w, TeamLds *tl,
+                          uint32_t *vis, int32_t *route, int32_t *pos, int2 *rxy, Draws &D,
+                          WinOut &o) {
   const int n = I.n, K = I.k, lane = lane_id();
+  const int g = w * kWave + lane;
+  o.v = -2;
+  o.dv = 0;
+  o.pv = 0;
+  o.lastq = u;
+  o.srcsum = 0;
   // every load below is addressed by source position: one round trip
-  const int rpos = wrap_off(pu, dir * lane, n);      // position of q_lane
-  const int qpos = wrap_off(pu, dir * (lane + 1), n);
-  const int qn = I.src_route[qpos];                   // q_{lane+1}
-  const int ed = I.src_d[dir > 0 ? rpos : qpos];      // cost q_lane -> q_{lane+1}
-  const size_t row = (size_t)rpos * (size_t)K;
+  const int rpos = wrap_off(pu, dir * g, n);      // position of q_g
+  const int qpos = wrap_off(pu, dir * (g + 1), n);
+  const int qn = I.src_route[qpos];                // q_{g+1}
+  const int ed = I.src_d[dir > 0 ? rpos : qpos];   // cost q_g -> q_{g+1}
+  const size_t row = srow(rpos, 0, K);
   int c[KT], sp[KT], cd[KT];
   float wt[KT];
 #pragma unroll
   for (int s = 0; s < KT; ++s) {
     if (s < K) {
-      c[s] = I.scl[row + s];
-      wt[s] = I.sw[row + s];
-      sp[s] = I.ssp[row + s];
-      cd[s] = I.sd[row + s];
+      c[s] = I.scl[row + 64 * s];
+      wt[s] = I.sw[row + 64 * s];
+      sp[s] = I.ssp[row + 64 * s];
+      cd[s] = I.sd[row + 64 * s];
     }
   }
-  // draws: a one-step window reuses the 64 draws computed for earlier steps
-  float U;
-  if (maxw == 1 && D.valid && step >= D.base && step < D.base + kWave) {
-    U = readlane_f(D.u, (int)(step - D.base));
-  } else {
-    D.u = unit24(philox_word0(I.seed, t, ant, step + (uint64_t)lane, kPurposeRoulette));
-    D.base = step;
-    D.valid = true;
-    U = D.u;
-  }
+  D.u = unit24(philox_word0(I.seed, t, ant, step + (uint64_t)g, kPurposeRoulette));
+  D.base = step + (uint64_t)(w * kWave);
+  D.valid = true;
+  const float U = D.u;
   float P[KT];
   float total = 0.0f;
   int last = -1;
@@ -239,7 +291,7 @@ FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
     if (s < K) {
       const int off = dir > 0 ? sp[s] - pu : pu - sp[s];
       const int offw = off < 0 ? off + n : off;
-      const bool visited = bit_get(vis, c[s]) || (offw >= 1 && offw <= lane);
+      const bool visited = bit_get(vis, c[s]) || (offw >= 1 && offw <= g);
       if (!visited) {
         total = total + wt[s];
         last = s;
@@ -264,26 +316,81 @@ FACO_DEV int spec_block(const Inst &I, uint64_t t, uint64_t ant, uint64_t step,
         choice_p = sp[s];
       }
   }
-  int valid = n - k < kWave ? n - k : kWave;  // steps left
+  int valid = n - k < TW * kWave ? n - k : TW * kWave;  // steps left
   valid = valid < maxw ? valid : maxw;
-  const bool match = !special && choice == qn && lane < valid;
+  const bool match = !special && choice == qn && g < valid;
   const uint64_t mm = ballot(!match);
-  const int f = mm ? ctz64(mm) : kWave;
-  const int acc = f < valid ? f : valid;  // accepted source-following steps
-  src_len_sum = wave_sum_i64(lane < acc ? (int64_t)ed : 0);
-  lastq = acc > 0 ? readlane_i(qn, acc - 1) : u;
-  if (acc < valid) {
-    if (readlane_i(special ? 1 : 0, acc)) {
-      v = -1;
+  int F = mm ? w * kWave + ctz64(mm) : TW * kWave;
+  if (TW > 1) {
+    if (lane == 0) tl->f[w] = F;
+    team_sync();  // every wave's evaluation is done before any append
+    F = wave_min_i32(lane < TW ? tl->f[lane] : 0x7fffffff);
+  }
+  const int acc = F < valid ? F : valid;
+  if (g < acc) {
+    route[k + g] = qn;
+    pos[qn] = k + g;
+    rxy[k + g] = I.xy[qn];
+    bit_set(vis, qn);
+  }
+  const int64_t ssum = wave_sum_i64(g < acc ? (int64_t)ed : 0);
+  o.acc = acc;
+  if (TW == 1) {
+    o.srcsum = ssum;
+    o.lastq = acc > 0 ? readlane_i(qn, acc - 1) : u;
+    if (acc < valid) {
+      if (readlane_i(special ? 1 : 0, acc)) {
+        o.v = -1;
+      } else {
+        o.v = readlane_i(choice, acc);
+        o.dv = readlane_i(choice_d, acc);
+        o.pv = readlane_i(choice_p, acc);
+      }
     } else {
-      v = readlane_i(choice, acc);
-      dv = readlane_i(choice_d, acc);
-      pv = readlane_i(choice_p, acc);
+      o.v = -2;
     }
   } else {
-    v = -2;  // every step of the window followed the source
+    // results for the leader, read after the closing barrier
+    if (lane == 0) tl->part[w] = ssum;
+    if (acc > 0 && g == acc - 1) tl->res[0] = qn;
+    if (acc < valid && g == acc) {
+      tl->res[1] = special ? -1 : choice;
+      tl->res[2] = choice_d;
+      tl->res[3] = choice_p;
+    }
+    o.v = acc < valid ? 0 : -2;
   }
-  return acc;
+}
+
+// Leader side of a window (TW > 1: posts it, takes wave 0's share, collects).
+template <int KT, int TW>
+FACO_DEV WinOut team_window(const Inst &I, uint64_t t, uint64_t ant, uint64_t step, int u,
+                            int pu, int dir, int k, int maxw, TeamLds *tl, uint32_t *vis,
+                            int32_t *route, int32_t *pos, int2 *rxy, Draws &D) {
+  WinOut o;
+  if (TW > 1) {
+    if (lane_id() == 0) {
+      tl->arg64[0] = t;
+      tl->arg64[1] = step;
+    }
+    team_post(tl, OP_WINDOW, u, pu, dir, k, maxw);
+  }
+  window_part<KT, TW>(I, t, ant, step, u, pu, dir, k, maxw, 0, tl, vis, route, pos, rxy, D,
+                      o);
+  if (TW > 1) {
+    team_sync();
+    o.acc = uniform_i(o.acc);
+    o.srcsum = wave_sum_i64(lane_id() < TW ? tl->part[lane_id()] : 0);
+    o.lastq = o.acc > 0 ? uniform_i(tl->res[0]) : u;
+    if (uniform_i(o.v) == 0) {
+      o.v = uniform_i(tl->res[1]);
+      o.dv = uniform_i(tl->res[2]);
+      o.pv = uniform_i(tl->res[3]);
+    } else {
+      o.v = -2;
+    }
+  }
+  return o;
 }
 
 // One ACO step from the city at source position pu, lane s = candidate slot
@@ -294,11 +401,11 @@ FACO_DEV int one_step(const Inst &I, uint64_t t, uint64_t ant, uint64_t step, in
   const int n = I.n, K = I.k, lane = lane_id();
   (void)n;
   const bool act = lane < K;
-  const size_t row = (size_t)pu * (size_t)K;
-  const int c = act ? I.scl[row + lane] : 0;
-  const float w = act ? I.sw[row + lane] : 0.0f;
-  const int sp = act ? I.ssp[row + lane] : 0;
-  const int d = act ? I.sd[row + lane] : 0;
+  const size_t row = srow(pu, act ? lane : 0, K);
+  const int c = act ? I.scl[row] : 0;
+  const float w = act ? I.sw[row] : 0.0f;
+  const int sp = act ? I.ssp[row] : 0;
+  const int d = act ? I.sd[row] : 0;
   const bool unv = act && !bit_get(vis, c);
   const uint64_t um = ballot(unv);
   if (!um) return -1;
@@ -340,10 +447,10 @@ FACO_DEV void append_city(const Inst &I, int v, int k, int32_t *route, int32_t *
 
 // tk: [5] speculative windows, [6] one-step calls, [7] copies, [8..10] their
 // ticks, [11] ticks in backup/nearest-city choices
-template <int KT>
+template <int KT, int TW>
 FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
                            int32_t *route, int32_t *pos, int2 *rxy, int32_t *ring,
-                           uint32_t *vis, uint32_t *inq, int W, int &nchk,
+                           uint32_t *vis, uint32_t *inq, TeamLds *tl, int W, int &nchk,
                            int64_t *cnt, int64_t *tk) {
   const int n = I.n, lane = lane_id();
   for (int w = lane; w < W; w += kWave) {
@@ -381,35 +488,39 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
     while (k < n) {
       // Once new_edges >= m every ACO step is followed by a copy, so the
       // window is one step wide.
-      const int maxw = new_edges >= I.m ? 1 : kWave;
-      int v, dv = 0, pv = 0, lastq = u;
-      int64_t srcsum = 0;
-      int acc = 0;
+      // loop state is wave-uniform; keep it in scalar registers so that the
+      // team barriers below sit in scalar control flow
+      k = uniform_i(k);
+      new_edges = uniform_i(new_edges);
+      u = uniform_i(u);
+      pu = uniform_i(pu);
+      dir = uniform_i(dir);
+      step = uniform_u64(step);
+      const int maxw = new_edges >= I.m ? 1 : TW * kWave;
+      int v, dv = 0, pv = 0;
       const int64_t c0 = ticks();
       if (maxw == 1) {
         v = one_step(I, t, (uint64_t)ant, step, pu, vis, D, dv, pv);
         tk[6]++;
         tk[9] += ticks() - c0;
       } else {
-        acc = spec_block<KT>(I, t, (uint64_t)ant, step, u, pu, dir, k, maxw, vis, D, v, dv,
-                             pv, lastq, srcsum);
+        // accepted steps follow the source: q_1..q_acc appended at k..k+acc-1
+        const WinOut o = team_window<KT, TW>(I, t, (uint64_t)ant, step, u, pu, dir, k, maxw,
+                                             tl, vis, route, pos, rxy, D);
         tk[5]++;
         tk[8] += ticks() - c0;
-      }
-      if (acc > 0) {
-        // accepted steps follow the source: q_1..q_acc at k..k+acc-1
-        if (lane < acc) {
-          const int q = I.src_route[wrap_off(pu, dir * (lane + 1), n)];
-          route[k + lane] = q;
-          pos[q] = k + lane;
-          rxy[k + lane] = I.xy[q];
-          bit_set(vis, q);
+        const int acc = uniform_i(o.acc);
+        v = uniform_i(o.v);
+        dv = uniform_i(o.dv);
+        pv = uniform_i(o.pv);
+        if (acc > 0) {
+          k += acc;
+          step += acc;
+          len += o.srcsum;
+          pu = wrap_off(pu, dir * acc, n);
+          u = uniform_i(o.lastq);
         }
-        k += acc;
-        step += acc;
-        len += srcsum;
-        pu = wrap_off(pu, dir * acc, n);
-        u = lastq;
+        wave_fence();
       }
       if (v == -2) {
         // the whole window followed the source; no step off the path
@@ -750,11 +861,15 @@ FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
 
 constexpr int kChunks = 16;  // 64-element chunks in flight per round
 
-// Reverse the cyclic array range of length L starting at s (wave-wide).
-FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos, int2 *rxy) {
+// Reverse the cyclic array range of length L starting at s: pairs (i,
+// L-1-i) are disjoint, so wave w of a team of TW takes every TW-th group of
+// kChunks * 64 pairs.
+template <int TW>
+FACO_DEV void reverse_part(int n, int s, int L, int w, int32_t *route, int32_t *pos,
+                           int2 *rxy) {
   const int lane = lane_id();
   const int half = L >> 1;
-  for (int base = 0; base < half; base += kChunks * kWave) {
+  for (int base = w * kChunks * kWave; base < half; base += TW * kChunks * kWave) {
     int p1[kChunks], p2[kChunks], v1[kChunks], v2[kChunks];
     int c1x[kChunks], c1y[kChunks], c2x[kChunks], c2y[kChunks];
 #pragma unroll
@@ -785,29 +900,91 @@ FACO_DEV void reverse_range(int n, int s, int L, int32_t *route, int32_t *pos, i
   }
 }
 
+// Move the cyclic block of D elements at src to dst = src -+ L (L <= 3,
+// D + L < n), keeping its order.  down: dst below src, rounds ascend; else
+// rounds descend.  A round reads TW * kChunks * 64 elements, then (after a
+// barrier when TW > 1) writes them: no round reads what a later-starting
+// write of another wave could clobber.
+template <int TW>
+FACO_DEV void shift_part(int n, int src, int dst, int D, bool down, int w, int32_t *route,
+                         int32_t *pos, int2 *rxy) {
+  const int lane = lane_id();
+  constexpr int R = TW * kChunks * kWave;
+  const int nr = (D + R - 1) / R;
+  for (int r = 0; r < nr; ++r) {
+    const int rb = (down ? r : nr - 1 - r) * R + w * kChunks * kWave;
+    int v[kChunks], cvx[kChunks], cvy[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+      const int i = rb + c * kWave + lane;
+      if (i < D) {
+        const int sp = wrap1(src + i, n);
+        v[c] = route[sp];
+        const int2 q = rxy[sp];
+        cvx[c] = q.x; cvy[c] = q.y;
+      }
+    }
+    if (TW > 1) team_sync();
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+      const int i = rb + c * kWave + lane;
+      if (i < D) {
+        const int d = wrap1(dst + i, n);
+        route[d] = v[c];
+        rxy[d] = make_int2(cvx[c], cvy[c]);
+        pos[v[c]] = d;
+      }
+    }
+  }
+}
+
+// Rewrites run by the leader alone when one round of its own covers them.
+template <int TW>
+FACO_DEV void team_reverse(int n, int s, int L, TeamLds *tl, int32_t *route, int32_t *pos,
+                           int2 *rxy) {
+  if (TW > 1 && (L >> 1) > kChunks * kWave) {
+    team_post(tl, OP_REVERSE, s, L);
+    reverse_part<TW>(n, s, L, 0, route, pos, rxy);
+    team_sync();
+  } else {
+    reverse_part<1>(n, s, L, 0, route, pos, rxy);
+    wave_fence();
+  }
+}
+template <int TW>
+FACO_DEV void team_shift(int n, int src, int dst, int D, bool down, TeamLds *tl,
+                         int32_t *route, int32_t *pos, int2 *rxy) {
+  if (TW > 1 && D > kChunks * kWave) {
+    team_post(tl, OP_SHIFT, src, dst, D, down ? 1 : 0);
+    shift_part<TW>(n, src, dst, D, down, 0, route, pos, rxy);
+    team_sync();
+  } else {
+    shift_part<1>(n, src, dst, D, down, 0, route, pos, rxy);
+    wave_fence();
+  }
+}
+
 // "Flip a section between x and y": the shorter of the paths x..y and z..w.
 // px, py, pz: array positions of x, y, z.
-FACO_DEV int apply_2opt(int n, int px, int py, int pz, int32_t *route,
+template <int TW>
+FACO_DEV int apply_2opt(int n, int px, int py, int pz, TeamLds *tl, int32_t *route,
                         int32_t *pos, int2 *rxy) {
   const int L1 = wrapn(py - px, n) + 1;
-  int moved;
   if (2 * L1 <= n) {
-    reverse_range(n, px, L1, route, pos, rxy);
-    moved = L1;
-  } else {
-    reverse_range(n, pz, n - L1, route, pos, rxy);
-    moved = n - L1;
+    team_reverse<TW>(n, px, L1, tl, route, pos, rxy);
+    return L1;
   }
-  wave_fence();
-  return moved;
+  team_reverse<TW>(n, pz, n - L1, tl, route, pos, rxy);
+  return n - L1;
 }
 
 // Or-opt: the segment and the shorter block between its old place and the
 // insertion edge exchange places (block keeps its orientation).
+template <int TW>
 FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
                          int pb, int fpos, int pq, int pp, int s0, int s1, int s2,
-                         int2 xs0, int2 xs1, int2 xs2, int32_t *route, int32_t *pos,
-                         int2 *rxy) {
+                         int2 xs0, int2 xs1, int2 xs2, TeamLds *tl, int32_t *route,
+                         int32_t *pos, int2 *rxy) {
   const int lane = lane_id();
   int x1, px1, px2;
   if (side == 0) {  // e = succ(b): edge (b, e)
@@ -836,29 +1013,7 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
   int moved;
   if (D1 <= D2) {
     // block q..x1 moves back by L to start at fpos; segment follows it
-    for (int base = 0; base < D1; base += kChunks * kWave) {
-      int v[kChunks], cvx[kChunks], cvy[kChunks];
-#pragma unroll
-      for (int c = 0; c < kChunks; ++c) {
-        const int i = base + c * kWave + lane;
-        if (i < D1) {
-          const int sp = wrap1(pq + i, n);
-          v[c] = route[sp];
-          const int2 q = rxy[sp];
-          cvx[c] = q.x; cvy[c] = q.y;
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < kChunks; ++c) {
-        const int i = base + c * kWave + lane;
-        if (i < D1) {
-          const int d = wrap1(fpos + i, n);
-          route[d] = v[c];
-          rxy[d] = make_int2(cvx[c], cvy[c]);
-          pos[v[c]] = d;
-        }
-      }
-    }
+    team_shift<TW>(n, pq, fpos, D1, true, tl, route, pos, rxy);
     if (lane < L) {
       const int d = wrapn(fpos + D1 + lane, n);
       route[d] = ins;
@@ -868,30 +1023,7 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
     moved = D1 + L;
   } else {
     // block x2..p moves forward by L; segment goes in front of it
-    const int top = ((D2 - 1) / (kChunks * kWave)) * (kChunks * kWave);
-    for (int base = top; base >= 0; base -= kChunks * kWave) {
-      int v[kChunks], cvx[kChunks], cvy[kChunks];
-#pragma unroll
-      for (int c = 0; c < kChunks; ++c) {
-        const int i = base + c * kWave + lane;
-        if (i < D2) {
-          const int sp = wrap1(px2 + i, n);
-          v[c] = route[sp];
-          const int2 q = rxy[sp];
-          cvx[c] = q.x; cvy[c] = q.y;
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < kChunks; ++c) {
-        const int i = base + c * kWave + lane;
-        if (i < D2) {
-          const int d = wrapn(px2 + L + i, n);
-          route[d] = v[c];
-          rxy[d] = make_int2(cvx[c], cvy[c]);
-          pos[v[c]] = d;
-        }
-      }
-    }
+    team_shift<TW>(n, px2, wrap1(px2 + L, n), D2, false, tl, route, pos, rxy);
     if (lane < L) {
       const int d = wrap1(px2 + lane, n);
       route[d] = ins;
@@ -925,22 +1057,52 @@ FACO_DEV void push(int n, int x, Queue &Q, int32_t *ring, uint32_t *inq,
 }
 
 // Sweep: test every touched city (ascending id) and list the improvable ones.
-template <int KT>
+// Cities are tested 64 TW at a time (wave w of the team takes the w-th 64);
+// the improvable ones are listed in ascending id.
+template <int KT, int TW>
+FACO_DEV void sweep_part(const Inst &I, uint32_t flags, int count, int w, const TeamLds *tl,
+                         const int32_t *route, const int32_t *pos, const int2 *rxy,
+                         TeamLds *out) {
+  const int i = w * kWave + lane_id();
+  bool f = false;
+  if (i < count) f = has_improving<KT>(I, flags, tl->cities[i], route, pos, rxy);
+  const uint64_t m = ballot(f);
+  if (lane_id() == 0) out->mask[w] = m;
+}
+
+template <int KT, int TW>
 FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
                    const int32_t *route, const int32_t *pos, const int2 *rxy, int32_t *ring,
-                   uint32_t *inq, uint32_t *touched) {
+                   uint32_t *inq, uint32_t *touched, TeamLds *tl) {
   const int lane = lane_id();
   int pushed = 0;
-  int bx = -1, bcount = 0;
+  int bx = -1, bcount = 0, nbuf = 0;
   auto flush = [&](int cnt) {
-    bool f = false;
-    if (lane < cnt) f = has_improving<KT>(I, flags, bx, route, pos, rxy);
-    uint64_t m = ballot(f);
-    while (m) {
-      const int l = ctz64(m);
-      m &= m - 1;
-      push(I.n, readlane_i(bx, l), Q, ring, inq, touched);
-      ++pushed;
+    if (TW == 1) {
+      bool f = false;
+      if (lane < cnt) f = has_improving<KT>(I, flags, bx, route, pos, rxy);
+      uint64_t m = ballot(f);
+      while (m) {
+        const int l = ctz64(m);
+        m &= m - 1;
+        push(I.n, readlane_i(bx, l), Q, ring, inq, touched);
+        ++pushed;
+      }
+      return;
+    }
+    // cnt cities sit in tl->cities[0..cnt)
+    team_post(tl, OP_SWEEP, cnt, (int)flags);
+    sweep_part<KT, TW>(I, flags, cnt, 0, tl, route, pos, rxy, tl);
+    team_sync();
+    for (int j = 0; j * kWave < cnt; ++j) {
+      const int c = tl->cities[j * kWave + lane];
+      uint64_t m = uniform_u64(tl->mask[j]);
+      while (m) {
+        const int l = ctz64(m);
+        m &= m - 1;
+        push(I.n, readlane_i(c, l), Q, ring, inq, touched);
+        ++pushed;
+      }
     }
   };
   for (int w0 = 0; w0 < W; w0 += kWave) {
@@ -956,21 +1118,34 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
         const int x = (w0 + l) * 32 + bpos;
         if (lane == bcount) bx = x;
         if (++bcount == kWave) {
-          flush(kWave);
+          if (TW == 1) {
+            flush(kWave);
+          } else {
+            tl->cities[nbuf * kWave + lane] = bx;
+            if (++nbuf == TW) {
+              flush(TW * kWave);
+              nbuf = 0;
+            }
+          }
           bcount = 0;
         }
       }
     }
   }
-  if (bcount) flush(bcount);
+  if (TW == 1) {
+    if (bcount) flush(bcount);
+  } else {
+    if (bcount) tl->cities[nbuf * kWave + lane] = bx;
+    const int cnt = nbuf * kWave + bcount;
+    if (cnt) flush(cnt);
+  }
   return pushed;
 }
 
-
-template <int KT>
+template <int KT, int TW>
 FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                               int32_t *pos, int2 *rxy, int32_t *ring, uint32_t *inq,
-                              uint32_t *touched, int W, Queue Q, int64_t *cnt,
+                              uint32_t *touched, TeamLds *tl, int W, Queue Q, int64_t *cnt,
                               int64_t *tk) {
   constexpr int GS = KT <= 16 ? 16 : 32;  // lanes per evaluated city
   constexpr int G = kWave / GS;           // cities evaluated together
@@ -978,7 +1153,11 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
   const int grp = lane / GS;
   int64_t changes = 0, gain = 0, changes_at_sweep = -1;
   for (;;) {
-    while (Q.count > 0 && changes < n) {
+    for (;;) {
+      Q.count = uniform_i(Q.count);
+      Q.head = uniform_i(Q.head);
+      Q.tail = uniform_i(Q.tail);
+      if (!(Q.count > 0 && changes < n)) break;
       // Evaluate the next G listed cities on the current tour.  The first one
       // with a move is applied; the ones before it are popped with no move;
       // the ones after it stay listed (their evaluation is discarded).
@@ -1018,8 +1197,9 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       }
       if (j >= gcount) continue;
       const Move mv = extract_move<GS>(I, R, j);
-      if (mv.kind == 1) {
-        cnt[CNT_MOVED_ELEMS] += apply_2opt(n, mv.px, mv.py, mv.pz, route, pos, rxy);
+      if (uniform_i(mv.kind) == 1) {
+        cnt[CNT_MOVED_ELEMS] += apply_2opt<TW>(n, uniform_i(mv.px), uniform_i(mv.py),
+                                               uniform_i(mv.pz), tl, route, pos, rxy);
         push(n, mv.w, Q, ring, inq, touched);
         push(n, mv.x, Q, ring, inq, touched);
         push(n, mv.y, Q, ring, inq, touched);
@@ -1027,8 +1207,10 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
         cnt[CNT_MOVES_2OPT]++;
       } else {
         cnt[CNT_MOVED_ELEMS] +=
-            apply_oropt(n, mv.L, mv.a, mv.f, mv.b, mv.e, mv.side, mv.pb, mv.fpos, mv.pq,
-                        mv.pp, mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2, route, pos, rxy);
+            apply_oropt<TW>(n, uniform_i(mv.L), mv.a, mv.f, mv.b, mv.e, uniform_i(mv.side),
+                            uniform_i(mv.pb), uniform_i(mv.fpos), uniform_i(mv.pq),
+                            uniform_i(mv.pp), mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2, tl,
+                            route, pos, rxy);
         push(n, mv.p, Q, ring, inq, touched);
         push(n, mv.q, Q, ring, inq, touched);
         push(n, mv.b, Q, ring, inq, touched);
@@ -1049,7 +1231,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     changes_at_sweep = changes;
     cnt[CNT_SWEEPS]++;
     const int64_t t2 = ticks();
-    const int pushed = sweep<KT>(I, flags, W, Q, route, pos, rxy, ring, inq, touched);
+    const int pushed = sweep<KT, TW>(I, flags, W, Q, route, pos, rxy, ring, inq, touched, tl);
     tk[3] += ticks() - t2;
     if (pushed == 0) break;
   }
@@ -1058,20 +1240,59 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
 }
 
 // ===================================================================== //
+// Helper waves of a team: wait for a command, take this wave's share, repeat
+// until the leader posts OP_EXIT.
+// ===================================================================== //
+template <int KT, int TW>
+FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *vis,
+                          int32_t *route, int32_t *pos, int2 *rxy) {
+  Draws D;
+  for (;;) {
+    team_sync();
+    const int op = uniform_i(tl->op);
+    if (op == OP_EXIT) break;
+    if (op == OP_REVERSE) {
+      reverse_part<TW>(I.n, team_arg(tl, 0), team_arg(tl, 1), w, route, pos, rxy);
+    } else if (op == OP_SHIFT) {
+      shift_part<TW>(I.n, team_arg(tl, 0), team_arg(tl, 1), team_arg(tl, 2),
+                     team_arg(tl, 3) != 0, w, route, pos, rxy);
+    } else if (op == OP_WINDOW) {
+      WinOut o;
+      window_part<KT, TW>(I, uniform_u64(tl->arg64[0]), (uint64_t)ant,
+                          uniform_u64(tl->arg64[1]), team_arg(tl, 0), team_arg(tl, 1),
+                          team_arg(tl, 2), team_arg(tl, 3), team_arg(tl, 4), w, tl, vis,
+                          route, pos, rxy, D, o);
+    } else if (op == OP_SWEEP) {
+      sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, route, pos,
+                         rxy, tl);
+    }
+    team_sync();
+  }
+}
+
+// ===================================================================== //
 // One ant: construction + local search.  mode 0: ant `ant` of iteration
 // st->iter + 1.  mode 1: initial solution (nearest neighbour + LS over all
-// cities) written to the global best.
+// cities) written to the global best.  lds: [team area][visited W][listed W].
 // ===================================================================== //
-template <int KT>
+template <int KT, int TW>
 FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   const int n = I.n, lane = lane_id();
   const int W = (n + 31) >> 5;
-  uint32_t *vis = lds;
-  uint32_t *inq = lds + W;
+  TeamLds *tl = (TeamLds *)lds;
+  uint32_t *vis = lds + team_words<TW>();
+  uint32_t *inq = vis + W;
   int32_t *route = I.routes + (size_t)ant * (size_t)n;
   int32_t *pos = I.pos + (size_t)ant * (size_t)n;
   int32_t *ring = I.ring + (size_t)ant * (size_t)n;
   int2 *rxy = I.rxy + (size_t)ant * (size_t)n;
+  if (TW > 1) {
+    const int w = uniform_i((int)(threadIdx.x >> 6));
+    if (w > 0) {
+      team_helper<KT, TW>(I, ant, w, tl, vis, route, pos, rxy);
+      return;
+    }
+  }
   int64_t cnt[NCNT];
 #pragma unroll
   for (int c = 0; c < NCNT; ++c) cnt[c] = 0;
@@ -1082,7 +1303,8 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   const uint64_t t = (uint64_t)I.st->iter + 1;
   int nchk = 0;
   const int64_t t0 = ticks();
-  int64_t len = construct<KT>(I, t, ant, init, route, pos, rxy, ring, vis, inq, W, nchk, cnt, tk);
+  int64_t len = construct<KT, TW>(I, t, ant, init, route, pos, rxy, ring, vis, inq, tl, W, nchk,
+                                  cnt, tk);
   tk[0] = ticks() - t0;
   uint32_t flags = I.ls_flags;
   Queue Q;
@@ -1113,7 +1335,11 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   }
   wave_fence();
   if (flags & (LS_2OPT | LS_OROPT))
-    len -= local_search<KT>(I, flags, route, pos, rxy, ring, inq, vis, W, Q, cnt, tk);
+    len -= local_search<KT, TW>(I, flags, route, pos, rxy, ring, inq, vis, tl, W, Q, cnt, tk);
+  if (TW > 1) {
+    if (lane == 0) tl->op = OP_EXIT;
+    team_sync();
+  }
   if (init) {
     for (int i = lane; i < n; i += kWave) I.gb_route[i] = route[i];
     if (lane == 0) {
@@ -1136,143 +1362,11 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   }
 }
 
-template <int KT>
-__global__ void __launch_bounds__(64) ant_kernel(Inst I, int mode) {
+// One workgroup of TW waves per ant.
+template <int KT, int TW>
+__global__ void __launch_bounds__(64 * TW) ant_kernel(Inst I, int mode) {
   extern __shared__ uint32_t lds[];
-  run_ant<KT>(I, (int)blockIdx.x, mode, lds);
-}
-
-// ===================================================================== //
-// Colony update (after the ants): iteration best, global best + limits
-// (Sec. 4.5), source choice.  One wave.
-// ===================================================================== //
-FACO_DEV void limits(const Inst &I, int64_t gb_len, float &tmin_f, float &tmax_f) {
-  const double tmax = 1.0 / ((double)gb_len * (1.0 - (double)I.rho));
-  const double num = 1.0 - I.p_root;
-  const double den = (double)(I.k - 1) * I.p_root;
-  double tmin = tmax * num / den;
-  if (tmin > tmax) tmin = tmax;
-  tmax_f = (float)tmax;
-  tmin_f = (float)tmin;
-}
-
-FACO_DEV void run_colony(const Inst &I) {
-  const int lane = lane_id();
-  DevState *st = I.st;
-  const uint64_t t = (uint64_t)st->iter + 1;
-  int64_t bl = INT64_MAX;
-  int ba = 0x7fffffff;
-  for (int a = lane; a < I.A; a += kWave) {
-    const int64_t L = I.lens[a];
-    if (L < bl) {
-      bl = L;
-      ba = a;
-    }
-  }
-  const int64_t minL = wave_min_i64(bl);
-  const int ib = wave_min_i32(bl == minL ? ba : 0x7fffffff);
-  int64_t gb = st->gb_len;
-  const bool improved = minL < gb;
-  float tmin = st->tau_min, tmax = st->tau_max;
-  if (improved) {
-    gb = minL;
-    limits(I, gb, tmin, tmax);
-  }
-  const uint64_t x = philox_word0(I.seed, t, ~0ull, 0, kPurposeSource);
-  const bool use_gb = (double)(uint32_t)(x >> 40) < I.p_gb * 16777216.0;
-  const int64_t src_len = use_gb ? gb : minL;
-  const float delta = (float)(1.0 / (double)src_len);
-  if (lane == 0) {
-    st->gb_len = gb;
-    st->tau_min = tmin;
-    st->tau_max = tmax;
-    st->ib = ib;
-    st->improved = improved ? 1 : 0;
-    st->src_gb = use_gb ? 1 : 0;
-    st->src_len = src_len;
-    st->delta = delta;
-    st->iter = (int64_t)t;
-  }
-}
-
-__global__ void __launch_bounds__(64) colony_kernel(Inst I) { run_colony(I); }
-
-// Source materialisation: the chosen tour becomes source_solution (route and
-// its inverse), the iteration best becomes the global best when it improved.
-// init: source := global best (before the first iteration).
-FACO_DEV void run_source(const Inst &I, int i, int init) {
-  const int n = I.n;
-  if (i >= n) return;
-  const DevState *st = I.st;
-  const int i1 = i + 1 == n ? 0 : i + 1, i0 = i == 0 ? n - 1 : i - 1;
-  const int32_t *from;
-  if (init) {
-    from = I.gb_route;
-  } else {
-    const int32_t *ibr = I.routes + (size_t)st->ib * (size_t)n;
-    from = (st->src_gb && !st->improved) ? I.gb_route : ibr;
-  }
-  const int node = from[i], next = from[i1], prev = from[i0];
-  if (!init && st->improved) I.gb_route[i] = node;
-  I.src_route[i] = node;
-  I.src_pos[node] = i;
-  I.src_adj[node] = make_int2(next, prev);
-  I.src_d[i] = cost(I.xy[node], I.xy[next]);
-}
-
-__global__ void __launch_bounds__(256) source_kernel(Inst I, int init) {
-  run_source(I, (int)(blockIdx.x * blockDim.x + threadIdx.x), init);
-}
-
-// Eq. (2) with the deposit on the source edges: tau' = clamp(rho tau + delta
-// [edge in source]).  init: tau = tau_max everywhere.
-FACO_DEV void run_pheromone(const Inst &I, size_t idx, int init) {
-  const int n = I.n, K = I.k;
-  if (idx >= (size_t)n * (size_t)K) return;
-  const DevState *st = I.st;
-  const float tmin = st->tau_min, tmax = st->tau_max;
-  const int j = I.cl[idx];
-  float tnew;
-  if (init) {
-    tnew = tmax;
-  } else {
-    const int i = (int)(idx / (size_t)K);
-    const int2 adj = I.src_adj[i];
-    const float t1 = I.rho * I.tau[idx];
-    float t2 = (j == adj.x || j == adj.y) ? t1 + st->delta : t1;
-    if (t2 > tmax) t2 = tmax;
-    if (t2 < tmin) t2 = tmin;
-    tnew = t2;
-  }
-  I.tau[idx] = tnew;
-  // candidate row of city i moved to row src_pos(i), read by the next
-  // construction: the city, its Eq. (1) weight, source position and cost
-  const int i = (int)(idx / (size_t)K), s = (int)(idx - (size_t)i * K);
-  const size_t o = (size_t)I.src_pos[i] * (size_t)K + s;
-  I.scl[o] = j;
-  I.sw[o] = tnew * I.eta[idx];
-  I.ssp[o] = I.src_pos[j];
-  I.sd[o] = I.cl_d[idx];
-}
-
-__global__ void __launch_bounds__(256) pheromone_kernel(Inst I, int init) {
-  run_pheromone(I, (size_t)blockIdx.x * blockDim.x + threadIdx.x, init);
-}
-
-// Limits of the initial solution; state before the first iteration.
-__global__ void init_state_kernel(Inst I) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  DevState *st = I.st;
-  float tmin, tmax;
-  limits(I, st->gb_len, tmin, tmax);
-  st->tau_min = tmin;
-  st->tau_max = tmax;
-  st->src_len = st->gb_len;
-  st->delta = 0.0f;
-  st->ib = -1;
-  st->src_gb = 0;
-  st->improved = 0;
-  st->iter = 0;
+  run_ant<KT, TW>(I, (int)blockIdx.x, mode, lds);
 }
 
 // ===================================================================== //
@@ -1290,77 +1384,7 @@ __global__ void __launch_bounds__(256) ant_batch_kernel(const Inst *insts, const
   const int w = (int)blockIdx.x * apb + wave;
   if (w >= total) return;
   const int2 m = amap[w];
-  run_ant<KT>(insts[m.x], m.y, 0, lds + (size_t)wave * (size_t)lds_words);
-}
-
-__global__ void __launch_bounds__(64) colony_batch_kernel(const Inst *insts) {
-  run_colony(insts[blockIdx.x]);
-}
-
-// blockIdx.y = instance; blocks past an instance's size return
-__global__ void __launch_bounds__(256) source_batch_kernel(const Inst *insts) {
-  run_source(insts[blockIdx.y], (int)(blockIdx.x * blockDim.x + threadIdx.x), 0);
-}
-
-__global__ void __launch_bounds__(256) pheromone_batch_kernel(const Inst *insts) {
-  run_pheromone(insts[blockIdx.y], (size_t)blockIdx.x * blockDim.x + threadIdx.x, 0);
-}
-
-// ===================================================================== //
-// Candidate + backup lists (Sec. 4.1): the K + BL nearest cities by
-// (squared distance, id); eta = 1/d.  One query city per lane; candidate
-// cities stream through LDS in tiles; each lane keeps its sorted list in LDS.
-// ===================================================================== //
-constexpr int kKnnTile = 256;
-
-__global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, int n, int K, int BL,
-                                                 int32_t *cl, int32_t *bll, float *eta,
-                                                 int32_t *cl_d, DevState *st) {
-  extern __shared__ unsigned char knn_lds[];
-  const int KK = K + BL;
-  const int tid = threadIdx.x;
-  int2 *tile = reinterpret_cast<int2 *>(knn_lds);
-  double *kd = reinterpret_cast<double *>(knn_lds + sizeof(int2) * kKnnTile);
-  int32_t *kj = reinterpret_cast<int32_t *>(knn_lds + sizeof(int2) * kKnnTile +
-                                            sizeof(double) * (size_t)KK * 64);
-  const int i = blockIdx.x * 64 + tid;
-  const bool valid = i < n;
-  const int2 xi = valid ? xy[i] : make_int2(0, 0);
-  int cnt = 0;
-  double worst = 0.0;
-  for (int t0 = 0; t0 < n; t0 += kKnnTile) {
-    __syncthreads();
-    for (int j = tid; j < kKnnTile; j += 64)
-      if (t0 + j < n) tile[j] = xy[t0 + j];
-    __syncthreads();
-    const int tn = min(kKnnTile, n - t0);
-    if (!valid) continue;
-    for (int jj = 0; jj < tn; ++jj) {
-      const int j = t0 + jj;
-      if (j == i) continue;
-      const double d = sqd(xi, tile[jj]);
-      if (cnt == KK && !(d < worst)) continue;
-      int q = cnt < KK ? cnt++ : KK - 1;
-      while (q > 0 && kd[(q - 1) * 64 + tid] > d) {
-        kd[q * 64 + tid] = kd[(q - 1) * 64 + tid];
-        kj[q * 64 + tid] = kj[(q - 1) * 64 + tid];
-        --q;
-      }
-      kd[q * 64 + tid] = d;
-      kj[q * 64 + tid] = j;
-      if (cnt == KK) worst = kd[(KK - 1) * 64 + tid];
-    }
-  }
-  if (!valid) return;
-  for (int s = 0; s < K; ++s) {
-    const double d2 = kd[s * 64 + tid];
-    cl[(size_t)i * K + s] = kj[s * 64 + tid];
-    const int d = (int)floor(sqrt(d2) + 0.5);
-    cl_d[(size_t)i * K + s] = d;
-    eta[(size_t)i * K + s] = (float)(1.0 / (double)d);
-  }
-  for (int s = 0; s < BL; ++s) bll[(size_t)i * BL + s] = kj[(K + s) * 64 + tid];
-  if (kd[tid] == 0.0) atomicOr(&st->dup, 1);
+  run_ant<KT, 1>(insts[m.x], m.y, 0, lds + (size_t)wave * (size_t)lds_words);
 }
 
 }  // namespace faco

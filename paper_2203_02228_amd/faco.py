@@ -18,7 +18,7 @@ FACO_LS_2OPT, FACO_LS_OROPT, FACO_LS_SWEEP = 1, 2, 4
 (FACO_DBG_ANT_ROUTES, FACO_DBG_ANT_LENGTHS, FACO_DBG_PHEROMONE, FACO_DBG_SOURCE,
  FACO_DBG_LIMITS, FACO_DBG_COUNTERS, FACO_DBG_CAND_LISTS, FACO_DBG_BACKUP_LISTS,
  FACO_DBG_HEURISTIC, FACO_DBG_INFO, FACO_DBG_INIT_COUNTERS,
- FACO_DBG_COUNTER_TOTALS, FACO_DBG_PHASE_TICKS) = range(13)
+ FACO_DBG_COUNTER_TOTALS, FACO_DBG_PHASE_TICKS, FACO_DBG_TEAM_WAVES) = range(14)
 CNT_NAMES = ["aco_steps", "copied", "backup", "fallback", "new_edges",
              "ls_pops", "moves_2opt", "moves_oropt", "moved_elems", "sweeps",
              "checklist0", "ls_gain"]
@@ -27,7 +27,7 @@ FACO_NCNT = len(CNT_NAMES)
 EXPORTED = ["faco_build_instance", "faco_run_iterations", "faco_get_best_tour",
             "faco_destroy_instance", "faco_last_error", "faco_run_batch",
             "faco_debug_get", "faco_footprint_bytes", "faco_set_timing",
-            "faco_phase_times", "faco_set_batch_ants_per_block"]
+            "faco_phase_times", "faco_set_batch_ants_per_block", "faco_set_team_waves"]
 
 
 class faco_params(ctypes.Structure):
@@ -84,6 +84,8 @@ def lib():
         L.faco_set_timing.argtypes = [vp, ctypes.c_int32]
         L.faco_set_batch_ants_per_block.restype = ctypes.c_int
         L.faco_set_batch_ants_per_block.argtypes = [ctypes.c_int32]
+        L.faco_set_team_waves.restype = ctypes.c_int
+        L.faco_set_team_waves.argtypes = [ctypes.c_int32]
         L.faco_phase_times.restype = ctypes.c_int
         L.faco_phase_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         _lib = L
@@ -173,6 +175,11 @@ def faco_set_batch_ants_per_block(apb):
     _check(lib().faco_set_batch_ants_per_block(int(apb)))
 
 
+def faco_set_team_waves(tw):
+    """Waves per ant for instances built afterwards (0 = by size; 1, 4, 8)."""
+    _check(lib().faco_set_team_waves(int(tw)))
+
+
 def faco_footprint_bytes(n, params=None, **kw):
     p = params if params is not None else make_params(**kw)
     return int(lib().faco_footprint_bytes(int(n), ctypes.byref(p)))
@@ -207,6 +214,7 @@ def faco_debug_get(inst, what):
         FACO_DBG_INIT_COUNTERS: (np.int64, (FACO_NCNT,)),
         FACO_DBG_COUNTER_TOTALS: (np.int64, (A, FACO_NCNT)),
         FACO_DBG_PHASE_TICKS: (np.int64, (A, 16)),
+        FACO_DBG_TEAM_WAVES: (np.int32, (1,)),
     }
     dt, shape = shapes[what]
     out = np.zeros(shape, dtype=dt)

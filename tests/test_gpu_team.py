@@ -1,0 +1,57 @@
+"""Ant teams (several waves per ant) against the oracle.
+
+With 4 or 8 waves per ant the speculative windows span 256 or 512 steps, the
+2-opt reversals and Or-opt block moves above one wave's round are split
+across the waves, and sweep tests run 64 cities per wave.  None of that may
+change a result: every iteration must match the oracle bit for bit, as the
+one-wave kernel does.  Cases cover tours shorter than one window, the
+window-only regime (m larger than n), Or-opt-only and 2-opt-only searches, and
+tours long enough (n >= 4096) for team reversals and shifts."""
+import pytest
+
+from paper_2203_02228_amd import faco as F
+from paper_2203_02228_amd import instances as I
+from tests.test_gpu_parity import _cmp_iter, _cmp_setup, _pair, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (5, "uniform", 2, dict(n_ants=4, min_new_edges=0, rho=0.2)),
+    (33, "cluster16", 5, dict(n_ants=4, min_new_edges=5, cl_size=7, bl_size=5,
+                              ls_flags=6, oropt_max_seg=2)),
+    (257, "uniform", 9, dict(n_ants=7, min_new_edges=6, rho=0.9, p_source_gbest=0.5)),
+    (300, "uniform", 11, dict(n_ants=6, min_new_edges=10**6, cl_size=5, bl_size=2)),
+    (700, "cluster16", 13, dict(n_ants=5, min_new_edges=12, ls_flags=1)),
+    (3000, "cluster16", 12, dict(n_ants=8, min_new_edges=40)),
+    (6000, "uniform", 14, dict(n_ants=6, min_new_edges=24, rho=0.8)),
+]
+
+
+@pytest.fixture(params=[4, 8])
+def team(request):
+    F.faco_set_team_waves(request.param)
+    try:
+        yield request.param
+    finally:
+        F.faco_set_team_waves(0)
+
+
+@pytest.mark.parametrize("n,kind,seed,params", CASES)
+def test_team_every_iteration(team, n, kind, seed, params):
+    say(f"[gpu] team={team} n={n} kind={kind} params={params}")
+    xy = I.make_points(kind, n, seed)
+    o, g = _pair(xy, threads=8, **params)
+    assert int(F.faco_debug_get(g, F.FACO_DBG_TEAM_WAVES)[0]) == team
+    _cmp_setup(o, g)
+    for it in range(1, 6):
+        o.run(1)
+        F.faco_run_iterations(g, 1)
+        _cmp_iter(o, g, it)
+    g.close()
+
+
+def test_team_setting_errors():
+    with pytest.raises(F.FacoError) as e:
+        F.faco_set_team_waves(3)
+    assert e.value.code == F.FACO_EINVAL
+    F.faco_set_team_waves(0)
