@@ -51,12 +51,15 @@ FACO_DEV int wrap_off(int q, int off, int n) {
 //   every wave alike); barrier; the leader reads what the op left in LDS.
 // ===================================================================== //
 constexpr int kMaxTeam = 8;
-enum TeamOp { OP_EXIT = 0, OP_REVERSE = 1, OP_SHIFT = 2, OP_WINDOW = 3, OP_SWEEP = 4 };
+enum TeamOp {
+  OP_EXIT = 0, OP_REVERSE = 1, OP_SHIFT = 2, OP_WINDOW = 3, OP_SWEEP = 4, OP_COPY = 5,
+  OP_NEAREST = 6
+};
 struct TeamLds {
   int op;
   int arg[11];
   uint64_t arg64[2];
-  int f[kMaxTeam];               // window: first step that left the source, per wave
+  int f[2 * kMaxTeam];           // per-wave first stop (window, copy: by round parity)
   int res[4];                    // window: last followed city; decision v, dv, pv
   int64_t part[kMaxTeam];        // window: per-wave sums of source edge costs
   uint64_t mask[kMaxTeam];       // sweep: per-wave ballots
@@ -85,7 +88,42 @@ FACO_DEV int team_arg(const TeamLds *tl, int i) { return uniform_i(tl->arg[i]); 
 // Backup list, then the nearest unvisited city (when no candidate of u is
 // unvisited).  Uniform result.
 // ===================================================================== //
-FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, int64_t *cnt) {
+// Nearest unvisited city to u by (squared distance, id): lane l of wave w
+// scans bitmap words w * 64 + l, + 64 TW, ...; fully visited words are
+// skipped.  Each wave leaves its (distance, city) minimum in LDS (TW > 1).
+template <int TW>
+FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, TeamLds *tl,
+                           int64_t &md, int &mj) {
+  const int lane = lane_id();
+  const int2 xu = I.xy[u];
+  const int W = (I.n + 31) >> 5;
+  int64_t bd = INT64_MAX;
+  int bj = 0x7fffffff;
+  for (int wi = w * kWave + lane; wi < W; wi += TW * kWave) {
+    uint32_t free_bits = ~vis[wi];
+    const int rem = I.n - wi * 32;
+    if (rem < 32) free_bits &= (1u << rem) - 1u;
+    while (free_bits) {
+      const int j = wi * 32 + __builtin_ctz(free_bits);
+      free_bits &= free_bits - 1;
+      const int64_t d = (int64_t)sqd_u64(xu, I.xy[j]);
+      if (d < bd) {
+        bd = d;
+        bj = j;
+      }
+    }
+  }
+  md = wave_min_i64(bd);
+  mj = wave_min_i32(bd == md ? bj : 0x7fffffff);
+  if (TW > 1 && lane == 0) {
+    tl->part[w] = md;
+    tl->f[w] = mj;
+  }
+}
+
+template <int TW>
+FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, TeamLds *tl,
+                             int64_t *cnt) {
   const int lane = lane_id();
   int b = 0;
   bool bu = false;
@@ -98,34 +136,27 @@ FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, int64_t 
     cnt[CNT_BACKUP]++;
     return readlane_i(b, ctz64(bm));
   }
-  // best heuristic value = nearest unvisited city, ties by smaller id.
-  // Lane l scans bitmap words l, l + 64, ...; fully visited words are skipped.
+  // best heuristic value = nearest unvisited city, ties by smaller id
   cnt[CNT_FALLBACK]++;
-  const int2 xu = I.xy[u];
-  const int W = (I.n + 31) >> 5;
-  int64_t bd = INT64_MAX;
-  int bj = 0x7fffffff;
-  for (int w = lane; w < W; w += kWave) {
-    uint32_t free_bits = ~vis[w];
-    const int rem = I.n - w * 32;
-    if (rem < 32) free_bits &= (1u << rem) - 1u;
-    while (free_bits) {
-      const int j = w * 32 + __builtin_ctz(free_bits);
-      free_bits &= free_bits - 1;
-      const int64_t d = (int64_t)sqd_u64(xu, I.xy[j]);
-      if (d < bd) {
-        bd = d;
-        bj = j;
-      }
-    }
+  int64_t md;
+  int mj;
+  if (TW == 1) {
+    nearest_part<1>(I, u, 0, vis, tl, md, mj);
+    return mj;
   }
-  const int64_t md = wave_min_i64(bd);
-  return wave_min_i32(bd == md ? bj : 0x7fffffff);
+  team_post(tl, OP_NEAREST, u);
+  nearest_part<TW>(I, u, 0, vis, tl, md, mj);
+  team_sync();
+  const int64_t d = lane < TW ? tl->part[lane] : INT64_MAX;
+  const int j = lane < TW ? tl->f[lane] : 0x7fffffff;
+  const int64_t dmin = wave_min_i64(d);
+  return uniform_i(wave_min_i32(d == dmin ? j : 0x7fffffff));
 }
 
 // Greedy step of the nearest-neighbour tour: first unvisited candidate
 // (lists are sorted by distance), else the fallback chain.  dv = its cost.
-FACO_DEV int select_greedy(const Inst &I, int u, const uint32_t *vis, int &dv,
+template <int TW>
+FACO_DEV int select_greedy(const Inst &I, int u, const uint32_t *vis, TeamLds *tl, int &dv,
                            int64_t *cnt) {
   const int K = I.k, lane = lane_id();
   const size_t row = (size_t)u * (size_t)K;
@@ -138,20 +169,95 @@ FACO_DEV int select_greedy(const Inst &I, int u, const uint32_t *vis, int &dv,
     dv = readlane_i(cd, s);
     return readlane_i(cand, s);
   }
-  const int v = select_fallback(I, u, vis, cnt);
+  const int v = select_fallback<TW>(I, u, vis, tl, cnt);
   dv = cost(I.xy[u], I.xy[v]);
   return v;
 }
 
 // ===================================================================== //
 // Copy-from-source (Alg. 2, reading: forward from v while unvisited, else
-// backward).  The first round probes 64 positions in both directions at
-// once; later rounds take 256 positions.  Edge costs come from the
-// per-iteration source edge table.  Returns the count; u/pu become the last
-// appended city and its source position.
+// backward).  The first probe looks 64 positions both ways at once; later
+// rounds take 256 positions per wave (64 TW * 4 per round for a team).
+// Edge costs come from the per-iteration source edge table.  Returns the
+// count; u/pu become the last appended city and its source position.
 // ===================================================================== //
+struct CopyOut {
+  int app;      // cities appended
+  int last;     // the last of them (-1: none)
+  int64_t sum;  // their edge costs
+};
+
+// Rounds from source position pcur in direction dir, appending at k.  A
+// round's cities lie past every earlier round's (the walk stops before it
+// could wrap onto them), so a round reads no visited bit another wave of the
+// same round sets.  The per-wave stops of consecutive rounds use alternate
+// LDS slots, so one barrier per round suffices.
+template <int TW>
+FACO_DEV void copy_rounds(const Inst &I, int pcur, int dir, int k, int w, TeamLds *tl,
+                          uint32_t *vis, int32_t *route, int32_t *pos, int2 *rxy,
+                          CopyOut &o) {
+  const int n = I.n, lane = lane_id();
+  constexpr int RW = 4 * kWave;  // positions per wave and round
+  int64_t dsum = 0;
+  int app = 0, last = -1;
+  for (int r = 0;; ++r) {
+    int cc[4], dd[4];
+    bool vc[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int q = wrap_off(pcur, dir * (w * RW + h * kWave + lane + 1), n);
+      cc[h] = I.src_route[q];
+      dd[h] = I.src_d[dir > 0 ? (q == 0 ? n - 1 : q - 1) : q];
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) vc[h] = bit_get(vis, cc[h]);
+    int jj = RW;
+#pragma unroll
+    for (int h = 3; h >= 0; --h) {
+      const uint64_t m = ballot(vc[h]);
+      if (m) jj = h * kWave + ctz64(m);
+    }
+    int J;
+    if (TW > 1) {
+      int *f = tl->f + (r & 1) * kMaxTeam;
+      if (lane == 0) f[w] = jj < RW ? w * RW + jj : TW * RW;
+      team_sync();
+      J = uniform_i(wave_min_i32(lane < TW ? f[lane] : 0x7fffffff));
+    } else {
+      J = jj;
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int idx = w * RW + h * kWave + lane;
+      if (idx < J) {
+        route[k + idx] = cc[h];
+        pos[cc[h]] = k + idx;
+        rxy[k + idx] = I.xy[cc[h]];
+        bit_set(vis, cc[h]);
+        dsum += dd[h];
+      }
+      if (idx == J - 1) {
+        if (TW > 1)
+          tl->res[0] = cc[h];
+        else
+          last = cc[h];
+      }
+    }
+    if (TW == 1 && J > 0) last = readlane_i(last, (J - 1) & (kWave - 1));
+    app += J;
+    k += J;
+    pcur = wrapn(pcur + dir * J, n);
+    if (J < TW * RW) break;
+  }
+  o.app = app;
+  o.last = last;
+  o.sum = wave_sum_i64(dsum);
+  if (TW > 1 && lane == 0) tl->part[w] = o.sum;
+}
+
+template <int TW>
 FACO_DEV int copy_from(const Inst &I, int pv, int &k, int &u, int &pu, int64_t &len,
-                       int32_t *route, int32_t *pos, int2 *rxy, uint32_t *vis) {
+                       TeamLds *tl, int32_t *route, int32_t *pos, int2 *rxy, uint32_t *vis) {
   const int n = I.n, lane = lane_id();
   const int qf = wrap_off(pv, lane + 1, n), qb = wrap_off(pv, -lane - 1, n);
   const int cf = I.src_route[qf], cb = I.src_route[qb];
@@ -175,51 +281,28 @@ FACO_DEV int copy_from(const Inst &I, int pv, int &k, int &u, int &pu, int64_t &
   len += wave_sum_i64(lane < j ? (int64_t)d : 0);
   u = readlane_i(c, j - 1);
   k += j;
-  int app = j, pcur = wrap_off(pv, dir * j, n);
+  const int pcur = wrap_off(pv, dir * j, n);
   if (j < kWave) {
     pu = pcur;
-    return app;
+    return j;
   }
-  for (;;) {
-    int cc[4], dd[4];
-    bool vc[4];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int q = wrap_off(pcur, dir * (h * kWave + lane + 1), n);
-      cc[h] = I.src_route[q];
-      dd[h] = I.src_d[dir > 0 ? (q == 0 ? n - 1 : q - 1) : q];
-    }
-#pragma unroll
-    for (int h = 0; h < 4; ++h) vc[h] = bit_get(vis, cc[h]);
-    int jj = 4 * kWave;
-#pragma unroll
-    for (int h = 3; h >= 0; --h) {
-      const uint64_t m = ballot(vc[h]);
-      if (m) jj = h * kWave + ctz64(m);
-    }
-    int64_t dsum = 0;
-    int last = 0;
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int idx = h * kWave + lane;
-      if (idx < jj) {
-        route[k + idx] = cc[h];
-        pos[cc[h]] = k + idx;
-        rxy[k + idx] = I.xy[cc[h]];
-        bit_set(vis, cc[h]);
-        dsum += dd[h];
-      }
-      if (idx == jj - 1) last = cc[h];
-    }
-    len += wave_sum_i64(dsum);
-    if (jj > 0) u = readlane_i(last, (jj - 1) & (kWave - 1));
-    k += jj;
-    app += jj;
-    pcur = wrapn(pcur + dir * jj, n);
-    if (jj < 4 * kWave) break;
+  CopyOut o;
+  if (TW > 1) {
+    team_post(tl, OP_COPY, pcur, dir, k);
+    copy_rounds<TW>(I, pcur, dir, k, 0, tl, vis, route, pos, rxy, o);
+    team_sync();
+    o.app = uniform_i(o.app);
+    o.sum = wave_sum_i64(lane < TW ? tl->part[lane] : 0);
+    o.last = o.app > 0 ? uniform_i(tl->res[0]) : -1;
+  } else {
+    wave_fence();
+    copy_rounds<1>(I, pcur, dir, k, 0, tl, vis, route, pos, rxy, o);
   }
-  pu = pcur;
-  return app;
+  len += o.sum;
+  if (o.app > 0) u = o.last;
+  k += o.app;
+  pu = wrapn(pcur + dir * o.app, n);
+  return j + o.app;
 }
 
 // ===================================================================== //
@@ -471,15 +554,15 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
   if (greedy) {
     while (k < n) {
       int dv;
-      const int v = select_greedy(I, u, vis, dv, cnt);
+      const int v = uniform_i(select_greedy<TW>(I, u, vis, tl, dv, cnt));
       ++step;
       len += dv;
       append_city(I, v, k, route, pos, rxy, vis);
-      ++k;
+      k = uniform_i(k + 1);
       u = v;
     }
   } else {
-    int pu = I.src_pos[u];
+    int pu = uniform_i(I.src_pos[u]);
     int dir = 1;
     Draws D;
     D.base = 0;
@@ -529,9 +612,9 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
       } else {
         if (v == -1) {
           const int64_t c1 = ticks();
-          v = select_fallback(I, u, vis, cnt);
-          dv = cost(I.xy[u], I.xy[v]);
-          pv = I.src_pos[v];
+          v = uniform_i(select_fallback<TW>(I, u, vis, tl, cnt));
+          dv = uniform_i(cost(I.xy[u], I.xy[v]));
+          pv = uniform_i(I.src_pos[v]);
           tk[11] += ticks() - c1;
         }
         ++step;
@@ -549,11 +632,14 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
         }
         dir = pv == bwd ? -1 : 1;
       }
-      u = v;
-      pu = pv;
+      u = uniform_i(v);
+      pu = uniform_i(pv);
+      new_edges = uniform_i(new_edges);
+      k = uniform_i(k);
+      dir = uniform_i(dir);
       if (new_edges >= I.m && k < n) {
         const int64_t c2 = ticks();
-        const int app = copy_from(I, pv, k, u, pu, len, route, pos, rxy, vis);
+        const int app = copy_from<TW>(I, pv, k, u, pu, len, tl, route, pos, rxy, vis);
         cnt[CNT_COPIED] += app;
         tk[7]++;
         tk[10] += ticks() - c2;
@@ -1151,12 +1237,15 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
   constexpr int G = kWave / GS;           // cities evaluated together
   const int n = I.n, lane = lane_id();
   const int grp = lane / GS;
-  int64_t changes = 0, gain = 0, changes_at_sweep = -1;
+  flags = (uint32_t)uniform_i((int)flags);
+  int changes = 0, changes_at_sweep = -1;
+  int64_t gain = 0;
   for (;;) {
     for (;;) {
       Q.count = uniform_i(Q.count);
       Q.head = uniform_i(Q.head);
       Q.tail = uniform_i(Q.tail);
+      changes = uniform_i(changes);
       if (!(Q.count > 0 && changes < n)) break;
       // Evaluate the next G listed cities on the current tour.  The first one
       // with a move is applied; the ones before it are popped with no move;
@@ -1223,6 +1312,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       ++changes;
       gain += mv.gain;
     }
+    changes = uniform_i(changes);
     if (!(flags & LS_SWEEP) || changes >= n) break;
     // Every city a sweep lists has an improving move, so a sweep that was
     // followed by no change can only come from the two evaluators disagreeing;
@@ -1231,7 +1321,8 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     changes_at_sweep = changes;
     cnt[CNT_SWEEPS]++;
     const int64_t t2 = ticks();
-    const int pushed = sweep<KT, TW>(I, flags, W, Q, route, pos, rxy, ring, inq, touched, tl);
+    const int pushed =
+        uniform_i(sweep<KT, TW>(I, flags, W, Q, route, pos, rxy, ring, inq, touched, tl));
     tk[3] += ticks() - t2;
     if (pushed == 0) break;
   }
@@ -1262,6 +1353,14 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
                           uniform_u64(tl->arg64[1]), team_arg(tl, 0), team_arg(tl, 1),
                           team_arg(tl, 2), team_arg(tl, 3), team_arg(tl, 4), w, tl, vis,
                           route, pos, rxy, D, o);
+    } else if (op == OP_COPY) {
+      CopyOut o;
+      copy_rounds<TW>(I, team_arg(tl, 0), team_arg(tl, 1), team_arg(tl, 2), w, tl, vis, route,
+                      pos, rxy, o);
+    } else if (op == OP_NEAREST) {
+      int64_t md;
+      int mj;
+      nearest_part<TW>(I, team_arg(tl, 0), w, vis, tl, md, mj);
     } else if (op == OP_SWEEP) {
       sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, route, pos,
                          rxy, tl);
@@ -1334,6 +1433,10 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
     if (flags & (LS_2OPT | LS_OROPT)) cnt[CNT_CHECKLIST0] = nchk;
   }
   wave_fence();
+  flags = (uint32_t)uniform_i((int)flags);
+  Q.head = uniform_i(Q.head);
+  Q.tail = uniform_i(Q.tail);
+  Q.count = uniform_i(Q.count);
   if (flags & (LS_2OPT | LS_OROPT))
     len -= local_search<KT, TW>(I, flags, route, pos, rxy, ring, inq, vis, tl, W, Q, cnt, tk);
   if (TW > 1) {
