@@ -131,6 +131,13 @@ int faco_set_batch_ants_per_block(int32_t ants_per_block);
  * changes results.  Errors: FACO_EINVAL. */
 int faco_set_team_waves(int32_t team_waves);
 
+/* Capacity (entries) of the LDS part of each ant's work queue of listed
+ * cities, for instances built after the call (process-wide): 0 for the
+ * default 16384, else 64..16384; an instance uses min(n, capacity).  A queue
+ * that outgrows it continues in global memory.  An execution-shape choice
+ * that never changes results.  Errors: FACO_EINVAL. */
+int faco_set_queue_lds_capacity(int32_t capacity);
+
 /* Debug / test dumps of the state after the last completed iteration.  Sync,
  * then copy `bytes` bytes into the host buffer `out`; `bytes` must equal the
  * size given below, otherwise FACO_EINVAL. */

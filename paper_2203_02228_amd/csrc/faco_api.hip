@@ -140,6 +140,22 @@ extern "C" int faco_set_team_waves(int32_t tw) {
   return FACO_OK;
 }
 
+// LDS capacity of an ant's work queue for instances built from now on.
+static int g_queue_lds_cap = faco::kLdsRingMax;
+
+extern "C" int faco_set_queue_lds_capacity(int32_t cap) {
+  if (cap != 0 && (cap < 64 || cap > faco::kLdsRingMax))
+    return set_err(nullptr, FACO_EINVAL, "queue LDS capacity must be 0 or in [64, 16384]");
+  std::lock_guard<std::mutex> lk(g_team_mu);
+  g_queue_lds_cap = cap ? cap : faco::kLdsRingMax;
+  return FACO_OK;
+}
+
+static int queue_lds_cap_for(int32_t n) {
+  std::lock_guard<std::mutex> lk(g_team_mu);
+  return n < g_queue_lds_cap ? n : g_queue_lds_cap;
+}
+
 static int team_waves_for(int32_t n, int32_t ants) {
   int tw;
   {
@@ -208,6 +224,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   I.bl = h->bl;
   I.A = p->n_ants;
   I.m = p->min_new_edges;
+  I.lcap = queue_lds_cap_for(n);
   I.rho = p->rho;
   I.ls_flags = p->ls_flags;
   I.oropt_max = p->oropt_max_seg;
@@ -284,7 +301,8 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
 
   h->tw = team_waves_for(n, p->n_ants);
   h->lds_ant = sizeof(uint32_t) * ((size_t)faco_team_lds_words(h->tw) +
-                                   2 * (size_t)((n + 31) / 32));
+                                   2 * (size_t)((n + 31) / 32) +
+                                   (size_t)I.lcap);
   BTRY(hipFuncSetAttribute((const void *)faco_ant_kernel(h->k, h->tw),
                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_ant));
   // initial solution (ant slot 0), limits, tau = tau_max, source = global best
@@ -424,6 +442,7 @@ extern "C" int faco_phase_times(faco_instance *h, double *ms_out, int64_t *launc
 // process-wide workspace that grows on demand; calls are serialised.
 
 
+static const size_t kLdsBytes = 160 * 1024;  // LDS of one CU (gfx950)
 static std::mutex g_batch_mu;
 static int g_batch_apb = 1;  // ants (waves) per workgroup in batched launches
 struct BatchWs {
@@ -469,14 +488,16 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
     insts[i] = h->dv;
     kmax = h->k > kmax ? h->k : kmax;
     maxn = h->n > maxn ? h->n : maxn;
-    const size_t words = 2 * (size_t)((h->n + 31) / 32);
+    const size_t words = 2 * (size_t)((h->n + 31) / 32) + (size_t)h->dv.lcap;
     lds_words = words > lds_words ? words : lds_words;
     const size_t slots = (size_t)h->n * (size_t)h->k;
     max_slots = slots > max_slots ? slots : max_slots;
     for (int a = 0; a < h->p.n_ants; ++a) amap.push_back(make_int2(i, a));
   }
   const int total = (int)amap.size();
-  const int apb = g_batch_apb;
+  // ants per workgroup: the setting, lowered until their LDS fits a CU
+  int apb = g_batch_apb;
+  while (apb > 1 && sizeof(uint32_t) * lds_words * (size_t)apb > kLdsBytes) apb >>= 1;
   const size_t lds_bytes = sizeof(uint32_t) * lds_words * (size_t)apb;
   // the tables are shared: the previous batch must be done with them
   if (!g_ws.last_done) BT(hipEventCreateWithFlags(&g_ws.last_done, hipEventDisableTiming));

@@ -30,6 +30,7 @@ struct DevState {
 //   cnt_acc   int64 [A][12]      the same summed over all iterations
 struct Inst {
   int32_t n, k, bl, A, m;
+  int32_t lcap;       // capacity of the LDS part of an ant's work queue
   float rho;
   uint32_t ls_flags;
   int32_t oropt_max;
@@ -87,5 +88,8 @@ constexpr int kMaxOrSeg = 3;
 __device__ __forceinline__ size_t srow(int p, int s, int k) {
   return ((size_t)(p >> 6) * (size_t)k + (size_t)s) * 64u + (size_t)(p & 63);
 }
+
+// Default capacity of the LDS part of an ant's work queue (listed cities).
+constexpr int kLdsRingMax = 16384;
 
 }  // namespace faco

@@ -700,6 +700,8 @@ FACO_DEV int64_t group_max(int64_t v) {
 // (slot s = lane % GS handles candidate s), 64 / GS cities per wave.
 struct GroupEval {
   int a, pa, b, pb, pbs, pbp, bs, bp, nb, d_ab;
+  int uc;          // lane s < 11: neighbourhood cost s of the group's city
+  int d_bs, d_bp;  // costs of b's tour edges
   int2 xa, xnb, xb, xbs, xbp;
   int64_t key2, keyo;  // group maxima: 2-opt, Or-opt (0 = none)
 };
@@ -736,12 +738,24 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
   R.pa = pa; R.b = b; R.pb = pb; R.pbs = pbs; R.pbp = pbp; R.bs = bs; R.bp = bp;
   R.nb = nb; R.xa = xa; R.xnb = xnb; R.xb = xb; R.xbs = xbs; R.xbp = xbp; R.d_ab = d_ab;
   const int2 xas = shfl_i2(xnb, gb + 4), xap = shfl_i2(xnb, gb + 2);
+  // Costs that depend only on the city's neighbourhood nb_0..nb_6 (tour
+  // positions pa-3..pa+3), one per lane of the group: the tour edges
+  // (nb_j, nb_j+1), j = 0..5, and the shortcuts (nb_2, nb_4), (nb_2, nb_5),
+  // (nb_2, nb_6), (nb_1, nb_4), (nb_0, nb_4) that close the gap a removed
+  // Or-opt segment leaves.  Consumers read them from the group's lanes.
+  {
+    const int su = s <= 5 ? s : (s <= 8 ? 2 : (s == 9 ? 1 : 0));
+    const int sv = s <= 5 ? s + 1 : (s <= 8 ? s - 2 : 4);
+    R.uc = cost(shfl_i2(xnb, gb + su), shfl_i2(xnb, gb + sv));
+  }
+  R.d_bs = cost(xb, xbs);
+  R.d_bp = cost(xbp, xb);
   R.key2 = 0;
   if (flags & LS_2OPT) {
-    const int d_as = cost(xa, xas), d_ap = cost(xap, xa);
+    const int d_as = __shfl(R.uc, gb + 3), d_ap = __shfl(R.uc, gb + 2);
     int g1 = 0, g2 = 0;
-    if (act && d_as > d_ab) g1 = d_as + cost(xb, xbs) - d_ab - cost(xas, xbs);
-    if (act && d_ap > d_ab) g2 = d_ap + cost(xbp, xb) - d_ab - cost(xap, xbp);
+    if (act && d_as > d_ab) g1 = d_as + R.d_bs - d_ab - cost(xas, xbs);
+    if (act && d_ap > d_ab) g2 = d_ap + R.d_bp - d_ab - cost(xap, xbp);
     const int64_t k1 = g1 > 0 ? (((int64_t)g1 << 8) | (int64_t)(255 - s)) : 0;
     const int64_t k2 = g2 > 0 ? (((int64_t)g2 << 8) | (int64_t)(255 - 32 - s)) : 0;
     R.key2 = group_max<GS>(k1 > k2 ? k1 : k2);
@@ -758,24 +772,28 @@ FACO_DEV void eval_group_oropt(const Inst &I, bool want, GroupEval &R) {
   const int s = lane & (GS - 1);
   const bool act = want && s < K;
   const int pa = R.pa, pb = R.pb, pbs = R.pbs, pbp = R.pbp, d_ab = R.d_ab;
-  const int2 xa = R.xa, xnb = R.xnb, xb = R.xb, xbs = R.xbs, xbp = R.xbp;
+  const int2 xnb = R.xnb, xbs = R.xbs, xbp = R.xbp;
   const int Lmax = or_lmax(I);
   int lbest = 0, lidx = 0;
-  const int d_bs = cost(xb, xbs), d_bp = cost(xb, xbp);
+  const int d_bs = R.d_bs, d_bp = R.d_bp;
+  int u[11];
+#pragma unroll
+  for (int j = 0; j < 11; ++j) u[j] = __shfl(R.uc, gb + j);
 #pragma unroll
   for (int vi = 0; vi < kOrSlots; ++vi) {
     int dir, L, lf, ll, lp, lq;
     or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
     if (L > Lmax) continue;
     const int2 xf = shfl_i2(xnb, gb + lf), xl = shfl_i2(xnb, gb + ll);
-    const int2 xp = shfl_i2(xnb, gb + lp), xq = shfl_i2(xnb, gb + lq);
     const int2 xo = dir == 0 ? xl : xf;
     const int fpos = dir == 0 ? pa : wrapn(pa - L + 1, n);
-    const int rem_a = dir == 0 ? cost(xp, xa) : cost(xa, xq);
+    // removal: (p, f) + (l, q) - (p, q); rem_a: the edge at a it removes
+    const int rem_a = dir == 0 ? u[2] : u[3];
+    const int g_rem = dir == 0 ? u[2] + u[2 + L] - u[5 + L]
+                               : u[3 - L] + u[3] - (L == 2 ? u[9] : u[10]);
     if (!act) continue;
     if (!(d_ab < rem_a)) continue;
     if (wrapn(pb - fpos, n) < L) continue;
-    const int g_rem = cost(xp, xf) + cost(xl, xq) - cost(xp, xq);
     if (wrapn(pbs - fpos, n) >= L) {
       const int g = g_rem + d_bs - d_ab - cost(xo, xbs);
       if (g > lbest) {
@@ -1122,22 +1140,42 @@ FACO_DEV int apply_oropt(int n, int L, int a, int f, int b, int e, int side,
   return moved;
 }
 
+// Work queue of listed cities (FIFO).  Entries sit in an LDS ring while they
+// fit (capacity I.lcap <= n), else in the ant's global ring (capacity n);
+// a full LDS ring moves its entries to the global ring, oldest first, and
+// the queue stays there.  Entries are written by lane 0; LDS operations of
+// one wave complete in order, and the global ring is read by lane 0 only.
 struct Queue {
   int head, tail, count;
+  int cap;      // capacity of the ring in use
+  int in_lds;   // 1: the LDS ring
+  int32_t *lr;  // LDS ring
+  int32_t *gr;  // global ring
 };
 
-// The ring is written and read by lane 0 only (program order makes its own
-// stores visible to it); the LDS bits are read by every lane, and LDS
-// operations of one wave complete in order.
-FACO_DEV void push(int n, int x, Queue &Q, int32_t *ring, uint32_t *inq,
-                   uint32_t *touched) {
-  if (!bit_get(inq, x)) {
+FACO_DEV void q_spill(Queue &Q, int n) {
+  const int lane = lane_id();
+  for (int i = lane; i < Q.count; i += kWave) {
+    int h = Q.head + i;
+    h = h >= Q.cap ? h - Q.cap : h;
+    Q.gr[i] = Q.lr[h];
+  }
+  wave_fence();
+  Q.head = 0;
+  Q.tail = Q.count == n ? 0 : Q.count;
+  Q.cap = n;
+  Q.in_lds = 0;
+}
+
+FACO_DEV void push(int n, int x, Queue &Q, uint32_t *inq, uint32_t *touched) {
+  if (!uniform_i(bit_get(inq, x) ? 1 : 0)) {
+    if (Q.in_lds && Q.count == Q.cap) q_spill(Q, n);
     if (lane_id() == 0) {
       bit_set(inq, x);
       bit_set(touched, x);
-      ring[Q.tail] = x;
+      (Q.in_lds ? Q.lr : Q.gr)[Q.tail] = x;
     }
-    Q.tail = Q.tail + 1 == n ? 0 : Q.tail + 1;
+    Q.tail = Q.tail + 1 == Q.cap ? 0 : Q.tail + 1;
     Q.count++;
   }
 }
@@ -1158,7 +1196,7 @@ FACO_DEV void sweep_part(const Inst &I, uint32_t flags, int count, int w, const 
 
 template <int KT, int TW>
 FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
-                   const int32_t *route, const int32_t *pos, const int2 *rxy, int32_t *ring,
+                   const int32_t *route, const int32_t *pos, const int2 *rxy,
                    uint32_t *inq, uint32_t *touched, TeamLds *tl) {
   const int lane = lane_id();
   int pushed = 0;
@@ -1171,7 +1209,7 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
       while (m) {
         const int l = ctz64(m);
         m &= m - 1;
-        push(I.n, readlane_i(bx, l), Q, ring, inq, touched);
+        push(I.n, readlane_i(bx, l), Q, inq, touched);
         ++pushed;
       }
       return;
@@ -1186,7 +1224,7 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
       while (m) {
         const int l = ctz64(m);
         m &= m - 1;
-        push(I.n, readlane_i(c, l), Q, ring, inq, touched);
+        push(I.n, readlane_i(c, l), Q, inq, touched);
         ++pushed;
       }
     }
@@ -1230,9 +1268,8 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
 
 template <int KT, int TW>
 FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
-                              int32_t *pos, int2 *rxy, int32_t *ring, uint32_t *inq,
-                              uint32_t *touched, TeamLds *tl, int W, Queue Q, int64_t *cnt,
-                              int64_t *tk) {
+                              int32_t *pos, int2 *rxy, uint32_t *inq, uint32_t *touched,
+                              TeamLds *tl, int W, Queue Q, int64_t *cnt, int64_t *tk) {
   constexpr int GS = KT <= 16 ? 16 : 32;  // lanes per evaluated city
   constexpr int G = kWave / GS;           // cities evaluated together
   const int n = I.n, lane = lane_id();
@@ -1245,6 +1282,8 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       Q.count = uniform_i(Q.count);
       Q.head = uniform_i(Q.head);
       Q.tail = uniform_i(Q.tail);
+      Q.cap = uniform_i(Q.cap);
+      Q.in_lds = uniform_i(Q.in_lds);
       changes = uniform_i(changes);
       if (!(Q.count > 0 && changes < n)) break;
       // Evaluate the next G listed cities on the current tour.  The first one
@@ -1252,11 +1291,19 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       // the ones after it stay listed (their evaluation is discarded).
       const int gcount = Q.count < G ? Q.count : G;
       int e[G];
+      if (Q.in_lds) {
+        int h = Q.head + lane;
+        h = h >= Q.cap ? h - Q.cap : h;
+        const int hv = lane < gcount ? Q.lr[h] : 0;
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        int h = Q.head + g;
-        h = h >= n ? h - n : h;
-        e[g] = readlane_i(lane == 0 && g < gcount ? ring[h] : 0, 0);
+        for (int g = 0; g < G; ++g) e[g] = readlane_i(hv, g);
+      } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          int h = Q.head + g;
+          h = h >= Q.cap ? h - Q.cap : h;
+          e[g] = readlane_i(lane == 0 && g < gcount ? Q.gr[h] : 0, 0);
+        }
       }
       int a = e[0];
 #pragma unroll
@@ -1279,7 +1326,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       for (int g = 0; g < G; ++g) {
         if (g < npop) {
           if (lane == 0) bit_clear(inq, e[g]);
-          Q.head = Q.head + 1 == n ? 0 : Q.head + 1;
+          Q.head = Q.head + 1 == Q.cap ? 0 : Q.head + 1;
           Q.count--;
           cnt[CNT_LS_POPS]++;
         }
@@ -1289,10 +1336,10 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       if (uniform_i(mv.kind) == 1) {
         cnt[CNT_MOVED_ELEMS] += apply_2opt<TW>(n, uniform_i(mv.px), uniform_i(mv.py),
                                                uniform_i(mv.pz), tl, route, pos, rxy);
-        push(n, mv.w, Q, ring, inq, touched);
-        push(n, mv.x, Q, ring, inq, touched);
-        push(n, mv.y, Q, ring, inq, touched);
-        push(n, mv.z, Q, ring, inq, touched);
+        push(n, mv.w, Q, inq, touched);
+        push(n, mv.x, Q, inq, touched);
+        push(n, mv.y, Q, inq, touched);
+        push(n, mv.z, Q, inq, touched);
         cnt[CNT_MOVES_2OPT]++;
       } else {
         cnt[CNT_MOVED_ELEMS] +=
@@ -1300,12 +1347,12 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                             uniform_i(mv.pb), uniform_i(mv.fpos), uniform_i(mv.pq),
                             uniform_i(mv.pp), mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2, tl,
                             route, pos, rxy);
-        push(n, mv.p, Q, ring, inq, touched);
-        push(n, mv.q, Q, ring, inq, touched);
-        push(n, mv.b, Q, ring, inq, touched);
-        push(n, mv.e, Q, ring, inq, touched);
-        push(n, mv.f, Q, ring, inq, touched);
-        push(n, mv.l, Q, ring, inq, touched);
+        push(n, mv.p, Q, inq, touched);
+        push(n, mv.q, Q, inq, touched);
+        push(n, mv.b, Q, inq, touched);
+        push(n, mv.e, Q, inq, touched);
+        push(n, mv.f, Q, inq, touched);
+        push(n, mv.l, Q, inq, touched);
         cnt[CNT_MOVES_OROPT]++;
       }
       tk[2] += ticks() - t1;
@@ -1322,7 +1369,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     cnt[CNT_SWEEPS]++;
     const int64_t t2 = ticks();
     const int pushed =
-        uniform_i(sweep<KT, TW>(I, flags, W, Q, route, pos, rxy, ring, inq, touched, tl));
+        uniform_i(sweep<KT, TW>(I, flags, W, Q, route, pos, rxy, inq, touched, tl));
     tk[3] += ticks() - t2;
     if (pushed == 0) break;
   }
@@ -1372,7 +1419,8 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
 // ===================================================================== //
 // One ant: construction + local search.  mode 0: ant `ant` of iteration
 // st->iter + 1.  mode 1: initial solution (nearest neighbour + LS over all
-// cities) written to the global best.  lds: [team area][visited W][listed W].
+// cities) written to the global best.
+//   lds: [team area][visited W][listed W][queue ring I.lcap].
 // ===================================================================== //
 template <int KT, int TW>
 FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
@@ -1406,39 +1454,50 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
                                   cnt, tk);
   tk[0] = ticks() - t0;
   uint32_t flags = I.ls_flags;
+  const int lcap = I.lcap;
   Queue Q;
+  Q.lr = (int32_t *)(inq + W);
+  Q.gr = ring;
   if (init) {
     // the initial solution reports only its local-search counters
 #pragma unroll
     for (int c = 0; c < CNT_LS_POPS; ++c) cnt[c] = 0;
     flags = LS_2OPT | LS_SWEEP | (I.ls_flags & LS_OROPT);
-    for (int i = lane; i < n; i += kWave) ring[i] = i;
+    Q.in_lds = n <= lcap ? 1 : 0;
+    Q.cap = Q.in_lds ? lcap : n;
+    for (int i = lane; i < n; i += kWave) (Q.in_lds ? Q.lr : ring)[i] = i;
     for (int w = lane; w < W; w += kWave) {
       const int rem = n - w * 32;
       const uint32_t full = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
       inq[w] = full;
       vis[w] = full;  // touched
     }
-    Q.head = 0;
-    Q.tail = 0;
     Q.count = n;
     cnt[CNT_CHECKLIST0] = n;
   } else {
     for (int w = lane; w < W; w += kWave) vis[w] = 0u;
     wave_fence();
-    for (int i = lane; i < nchk; i += kWave) bit_set(vis, ring[i]);
-    Q.head = 0;
-    Q.tail = nchk;
+    Q.in_lds = nchk <= lcap ? 1 : 0;
+    Q.cap = Q.in_lds ? lcap : n;
+    for (int i = lane; i < nchk; i += kWave) {
+      const int c = ring[i];
+      bit_set(vis, c);
+      if (Q.in_lds) Q.lr[i] = c;
+    }
     Q.count = nchk;
     if (flags & (LS_2OPT | LS_OROPT)) cnt[CNT_CHECKLIST0] = nchk;
   }
+  Q.head = 0;
+  Q.tail = Q.count == Q.cap ? 0 : Q.count;
   wave_fence();
   flags = (uint32_t)uniform_i((int)flags);
   Q.head = uniform_i(Q.head);
   Q.tail = uniform_i(Q.tail);
   Q.count = uniform_i(Q.count);
+  Q.cap = uniform_i(Q.cap);
+  Q.in_lds = uniform_i(Q.in_lds);
   if (flags & (LS_2OPT | LS_OROPT))
-    len -= local_search<KT, TW>(I, flags, route, pos, rxy, ring, inq, vis, tl, W, Q, cnt, tk);
+    len -= local_search<KT, TW>(I, flags, route, pos, rxy, inq, vis, tl, W, Q, cnt, tk);
   if (TW > 1) {
     if (lane == 0) tl->op = OP_EXIT;
     team_sync();

@@ -27,7 +27,8 @@ FACO_NCNT = len(CNT_NAMES)
 EXPORTED = ["faco_build_instance", "faco_run_iterations", "faco_get_best_tour",
             "faco_destroy_instance", "faco_last_error", "faco_run_batch",
             "faco_debug_get", "faco_footprint_bytes", "faco_set_timing",
-            "faco_phase_times", "faco_set_batch_ants_per_block", "faco_set_team_waves"]
+            "faco_phase_times", "faco_set_batch_ants_per_block", "faco_set_team_waves",
+            "faco_set_queue_lds_capacity"]
 
 
 class faco_params(ctypes.Structure):
@@ -86,6 +87,8 @@ def lib():
         L.faco_set_batch_ants_per_block.argtypes = [ctypes.c_int32]
         L.faco_set_team_waves.restype = ctypes.c_int
         L.faco_set_team_waves.argtypes = [ctypes.c_int32]
+        L.faco_set_queue_lds_capacity.restype = ctypes.c_int
+        L.faco_set_queue_lds_capacity.argtypes = [ctypes.c_int32]
         L.faco_phase_times.restype = ctypes.c_int
         L.faco_phase_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         _lib = L
@@ -173,6 +176,12 @@ def faco_run_batch(insts, iterations, stream=None):
 
 def faco_set_batch_ants_per_block(apb):
     _check(lib().faco_set_batch_ants_per_block(int(apb)))
+
+
+def faco_set_queue_lds_capacity(cap):
+    """LDS capacity of each ant's work queue for instances built afterwards
+    (0 = default)."""
+    _check(lib().faco_set_queue_lds_capacity(int(cap)))
 
 
 def faco_set_team_waves(tw):

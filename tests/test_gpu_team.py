@@ -55,3 +55,36 @@ def test_team_setting_errors():
         F.faco_set_team_waves(3)
     assert e.value.code == F.FACO_EINVAL
     F.faco_set_team_waves(0)
+
+
+@pytest.mark.parametrize("tw,n,kind,seed,params", [
+    (1, 700, "cluster16", 13, dict(n_ants=5, min_new_edges=30)),
+    (4, 3000, "cluster16", 12, dict(n_ants=8, min_new_edges=40)),
+    (8, 6000, "uniform", 14, dict(n_ants=6, min_new_edges=60, rho=0.8)),
+])
+def test_small_lds_queue_spills(tw, n, kind, seed, params):
+    """A 64-entry LDS queue: the initial search starts in the global ring and
+    iterations overflow the LDS ring into it; results must not change."""
+    say(f"[gpu] lds queue 64 team={tw} n={n} params={params}")
+    F.faco_set_team_waves(tw)
+    F.faco_set_queue_lds_capacity(64)
+    try:
+        xy = I.make_points(kind, n, seed)
+        o, g = _pair(xy, threads=8, **params)
+    finally:
+        F.faco_set_queue_lds_capacity(0)
+        F.faco_set_team_waves(0)
+    _cmp_setup(o, g)
+    for it in range(1, 5):
+        o.run(1)
+        F.faco_run_iterations(g, 1)
+        _cmp_iter(o, g, it)
+    g.close()
+
+
+def test_queue_capacity_errors():
+    for bad in (1, 63, 16385, -5):
+        with pytest.raises(F.FacoError) as e:
+            F.faco_set_queue_lds_capacity(bad)
+        assert e.value.code == F.FACO_EINVAL
+    F.faco_set_queue_lds_capacity(0)
