@@ -99,9 +99,7 @@ FACO_DEV void bit_clear(uint32_t *bm, int x) {
 
 // ---------------------------------------------------------------- cost ---
 // TSPLIB EUC_2D: nint(sqrt(dx^2 + dy^2)).  With |dx|,|dy| < 2^23 the squared
-// length is an exact integer below 2^47.  A binary32 square root estimates
-// floor(sqrt(d2)) to within 2; integer checks make it exact, and nint is
-// r + [d2 > r^2 + r] (sqrt(d2) is never exactly a half-integer).
+// length is an exact integer below 2^47.
 
 FACO_DEV double sqd(int2 a, int2 b) {
   double dx = (double)(a.x - b.x);
@@ -114,14 +112,14 @@ FACO_DEV uint64_t sqd_u64(int2 a, int2 b) {
   return (uint64_t)ax * ax + (uint64_t)ay * ay;
 }
 FACO_DEV int cost(int2 a, int2 b) {
-  const uint64_t d2 = sqd_u64(a, b);
-  // estimate within [floor - 2, floor + 1] (binary32: relative error < 2^-23)
-  uint32_t r = (uint32_t)__fsqrt_rn((float)d2);
-  r -= ((uint64_t)r * r > d2) ? 1u : 0u;
-  r -= ((uint64_t)r * r > d2) ? 1u : 0u;
-  r += ((uint64_t)(r + 1) * (r + 1) <= d2) ? 1u : 0u;
-  r += ((uint64_t)(r + 1) * (r + 1) <= d2) ? 1u : 0u;
-  return (int)r + (d2 > (uint64_t)r * r + r ? 1 : 0);
+  // dx^2 + dy^2 < 2^47 is exact in binary64; the correctly rounded square
+  // root s' of d2 is within 2^-29.5 of s = sqrt(d2) < 2^23.5 and s' + 0.5 is
+  // within 2^-28.5 of s + 0.5, while s is at least 0.25 / (2 s + 1) > 2^-26.5
+  // away from any half-integer (d2 is an integer): the truncation of s' + 0.5
+  // is exactly nint(s).  Binary64 vector operations run at full rate.
+  const double dx = (double)(a.x - b.x), dy = (double)(a.y - b.y);
+  const double d2 = dx * dx + dy * dy;
+  return (int)(__dsqrt_rn(d2) + 0.5);
 }
 
 // ----------------------------------------------------------- Philox4x64 ---
