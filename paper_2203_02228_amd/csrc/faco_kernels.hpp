@@ -963,22 +963,26 @@ FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
   return false;
 }
 
-constexpr int kChunks = 16;  // 64-element chunks in flight per round
+constexpr int kChunks = 16;  // 64-element chunks in flight per wave and round
+// Rewrites of more pairs than this (elements, for block moves: twice this)
+// are shared by the team; shorter ones are the leader's alone.
+constexpr int kTeamMinPairs = 256;
 
 // Reverse the cyclic array range of length L starting at s: pairs (i,
-// L-1-i) are disjoint, so wave w of a team of TW takes every TW-th group of
-// kChunks * 64 pairs.
+// L-1-i) are disjoint, so the 64-pair chunks are dealt to the waves of a
+// team of TW in turn (chunk c to wave c mod TW), kChunks per wave in flight.
 template <int TW>
 FACO_DEV void reverse_part(int n, int s, int L, int w, int32_t *route, int32_t *pos,
                            int2 *rxy) {
   const int lane = lane_id();
   const int half = L >> 1;
-  for (int base = w * kChunks * kWave; base < half; base += TW * kChunks * kWave) {
+  const int nch = (half + kWave - 1) / kWave;
+  for (int c0 = w; c0 < nch; c0 += TW * kChunks) {
     int p1[kChunks], p2[kChunks], v1[kChunks], v2[kChunks];
     int c1x[kChunks], c1y[kChunks], c2x[kChunks], c2y[kChunks];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-      const int i = base + c * kWave + lane;
+      const int i = (c0 + c * TW) * kWave + lane;
       if (i < half) {
         p1[c] = wrap1(s + i, n);
         p2[c] = wrap1(s + L - 1 - i, n);
@@ -991,7 +995,7 @@ FACO_DEV void reverse_part(int n, int s, int L, int w, int32_t *route, int32_t *
     }
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-      const int i = base + c * kWave + lane;
+      const int i = (c0 + c * TW) * kWave + lane;
       if (i < half) {
         route[p1[c]] = v2[c];
         route[p2[c]] = v1[c];
@@ -1016,11 +1020,12 @@ FACO_DEV void shift_part(int n, int src, int dst, int D, bool down, int w, int32
   constexpr int R = TW * kChunks * kWave;
   const int nr = (D + R - 1) / R;
   for (int r = 0; r < nr; ++r) {
-    const int rb = (down ? r : nr - 1 - r) * R + w * kChunks * kWave;
+    // round r covers elements [rb, rb + R); its chunks go to the waves in turn
+    const int rb = (down ? r : nr - 1 - r) * R;
     int v[kChunks], cvx[kChunks], cvy[kChunks];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-      const int i = rb + c * kWave + lane;
+      const int i = rb + (w + c * TW) * kWave + lane;
       if (i < D) {
         const int sp = wrap1(src + i, n);
         v[c] = route[sp];
@@ -1031,7 +1036,7 @@ FACO_DEV void shift_part(int n, int src, int dst, int D, bool down, int w, int32
     if (TW > 1) team_sync();
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-      const int i = rb + c * kWave + lane;
+      const int i = rb + (w + c * TW) * kWave + lane;
       if (i < D) {
         const int d = wrap1(dst + i, n);
         route[d] = v[c];
@@ -1046,7 +1051,7 @@ FACO_DEV void shift_part(int n, int src, int dst, int D, bool down, int w, int32
 template <int TW>
 FACO_DEV void team_reverse(int n, int s, int L, TeamLds *tl, int32_t *route, int32_t *pos,
                            int2 *rxy) {
-  if (TW > 1 && (L >> 1) > kChunks * kWave) {
+  if (TW > 1 && (L >> 1) > kTeamMinPairs) {
     team_post(tl, OP_REVERSE, s, L);
     reverse_part<TW>(n, s, L, 0, route, pos, rxy);
     team_sync();
@@ -1058,7 +1063,7 @@ FACO_DEV void team_reverse(int n, int s, int L, TeamLds *tl, int32_t *route, int
 template <int TW>
 FACO_DEV void team_shift(int n, int src, int dst, int D, bool down, TeamLds *tl,
                          int32_t *route, int32_t *pos, int2 *rxy) {
-  if (TW > 1 && D > kChunks * kWave) {
+  if (TW > 1 && D > 2 * kTeamMinPairs) {
     team_post(tl, OP_SHIFT, src, dst, D, down ? 1 : 0);
     shift_part<TW>(n, src, dst, D, down, 0, route, pos, rxy);
     team_sync();
