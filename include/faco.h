@@ -117,14 +117,16 @@ const char *faco_last_error(const faco_instance *h);
 int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
                    void *hip_stream);
 
-/* Ants (wavefronts) per workgroup in faco_run_batch launches: 1, 2 or 4
- * (process-wide; an execution-shape choice that never changes results).
+/* Ants (wavefronts) per workgroup in faco_run_batch launches with one wave
+ * per ant: 1, 2 or 4, lowered when their LDS would not fit a CU (process-
+ * wide; an execution-shape choice that never changes results).
  * Errors: FACO_EINVAL. */
 int faco_set_batch_ants_per_block(int32_t ants_per_block);
 
-/* Waves per ant in the per-instance ant kernel, for instances built after
- * the call (process-wide): 1, 4 or 8, or 0 for a choice by size (1 below
- * 2048 cities; else 8 up to 256 ants, 4 up to 512, 1 beyond).  Wave 0 of an
+/* Waves per ant in the ant kernels, for instances built after the call and
+ * for faco_run_batch launches after it (process-wide): 1, 4 or 8, or 0 for a
+ * choice by size (1 below 2048 cities; else 8 up to 256 ants, 4 up to 512,
+ * 1 beyond; a batch counts its largest tour and all its ants).  Wave 0 of an
  * ant makes every decision; the others share its wide steps (speculative
  * source-following windows of 64 steps per wave, the array rewrites of 2-opt
  * and Or-opt moves, sweep tests).  An execution-shape choice that never

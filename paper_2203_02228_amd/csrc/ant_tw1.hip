@@ -11,6 +11,15 @@ AntKernelFn faco_ant_kernel_tw1(int k) {
   return faco::ant_kernel<32, 1>;
 }
 
+AntBatchFn faco_ant_batch_kernel_tw1(int k) {
+  if (k <= 4) return faco::ant_batch_kernel<4, 1>;
+  if (k <= 8) return faco::ant_batch_kernel<8, 1>;
+  if (k <= 12) return faco::ant_batch_kernel<12, 1>;
+  if (k <= 16) return faco::ant_batch_kernel<16, 1>;
+  if (k <= 24) return faco::ant_batch_kernel<24, 1>;
+  return faco::ant_batch_kernel<32, 1>;
+}
+
 AntKernelFn faco_ant_kernel_tw4(int k);
 AntKernelFn faco_ant_kernel_tw8(int k);
 
@@ -21,13 +30,14 @@ AntKernelFn faco_ant_kernel(int k, int tw) {
   return nullptr;
 }
 
-AntBatchFn faco_ant_batch_kernel(int k) {
-  if (k <= 4) return faco::ant_batch_kernel<4>;
-  if (k <= 8) return faco::ant_batch_kernel<8>;
-  if (k <= 12) return faco::ant_batch_kernel<12>;
-  if (k <= 16) return faco::ant_batch_kernel<16>;
-  if (k <= 24) return faco::ant_batch_kernel<24>;
-  return faco::ant_batch_kernel<32>;
+AntBatchFn faco_ant_batch_kernel_tw4(int k);
+AntBatchFn faco_ant_batch_kernel_tw8(int k);
+
+AntBatchFn faco_ant_batch_kernel(int k, int tw) {
+  if (tw == 1) return faco_ant_batch_kernel_tw1(k);
+  if (tw == 4) return faco_ant_batch_kernel_tw4(k);
+  if (tw == 8) return faco_ant_batch_kernel_tw8(k);
+  return nullptr;
 }
 
 int faco_team_lds_words(int tw) {

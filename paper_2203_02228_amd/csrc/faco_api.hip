@@ -102,8 +102,17 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   return b;
 }
 
+// Held while a batch graph is being captured, and around device allocation
+// and release, which may synchronise implicitly and must not meet a capture
+// in progress on another thread.
+static std::mutex g_capture_mu;
+
 static int dalloc(faco_instance *h, void **ptr, size_t bytes) {
-  hipError_t e = hipMalloc(ptr, bytes ? bytes : 4);
+  hipError_t e;
+  {
+    std::lock_guard<std::mutex> lk(g_capture_mu);
+    e = hipMalloc(ptr, bytes ? bytes : 4);
+  }
   if (e != hipSuccess) {
     *ptr = nullptr;
     return set_err(h, FACO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -331,15 +340,22 @@ extern "C" int faco_run_iterations(faco_instance *h, int32_t iterations) {
   return FACO_OK;
 }
 
+// Device-to-host copy on the handle's stream, then wait for it.  (The
+// legacy stream is avoided: another thread may be capturing a batch graph.)
+static hipError_t d2h(faco_instance *h, void *dst, const void *src, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(h->stream);
+}
+
 extern "C" int faco_get_best_tour(faco_instance *h, int32_t *tour_out, int64_t *length_out) {
   if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   if (tour_out)
-    HIP_TRY(h, hipMemcpy(tour_out, h->dv.gb_route, sizeof(int32_t) * (size_t)h->n,
-                         hipMemcpyDeviceToHost));
+    HIP_TRY(h, d2h(h, tour_out, h->dv.gb_route, sizeof(int32_t) * (size_t)h->n));
   if (length_out) {
     DevState hs;
-    HIP_TRY(h, hipMemcpy(&hs, h->dv.st, sizeof(DevState), hipMemcpyDeviceToHost));
+    HIP_TRY(h, d2h(h, &hs, h->dv.st, sizeof(DevState)));
     *length_out = hs.gb_len;
   }
   return FACO_OK;
@@ -352,7 +368,10 @@ extern "C" void faco_destroy_instance(faco_instance *h) {
     (void)hipEventDestroy(tl.a);
     (void)hipEventDestroy(tl.b);
   }
-  for (void *p : h->allocs) (void)hipFree(p);
+  {
+    std::lock_guard<std::mutex> lk(g_capture_mu);
+    for (void *p : h->allocs) (void)hipFree(p);
+  }
   delete h;
 }
 
@@ -368,7 +387,7 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
   size_t need = 0;
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   DevState hs;
-  HIP_TRY(h, hipMemcpy(&hs, h->dv.st, sizeof(DevState), hipMemcpyDeviceToHost));
+  HIP_TRY(h, d2h(h, &hs, h->dv.st, sizeof(DevState)));
   switch (what) {
     case FACO_DBG_ANT_ROUTES: src = h->dv.routes; need = 4 * N * A; break;
     case FACO_DBG_ANT_LENGTHS: src = h->dv.lens; need = 8 * A; break;
@@ -406,7 +425,7 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
     default: return set_err(h, FACO_EINVAL, "unknown dump");
   }
   if (bytes != need) return set_err(h, FACO_EINVAL, "size mismatch");
-  if (need) HIP_TRY(h, hipMemcpy(out, src, need, hipMemcpyDeviceToHost));
+  if (need) HIP_TRY(h, d2h(h, out, src, need));
   return FACO_OK;
 }
 
@@ -495,16 +514,21 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
     for (int a = 0; a < h->p.n_ants; ++a) amap.push_back(make_int2(i, a));
   }
   const int total = (int)amap.size();
-  // ants per workgroup: the setting, lowered until their LDS fits a CU
-  int apb = g_batch_apb;
+  // waves per ant (as for a lone instance, from the largest tour and the
+  // ant count); with one wave per ant, ants per workgroup: the setting,
+  // lowered until their LDS fits a CU
+  const int tw = team_waves_for(maxn, total);
+  int apb = tw > 1 ? 1 : g_batch_apb;
   while (apb > 1 && sizeof(uint32_t) * lds_words * (size_t)apb > kLdsBytes) apb >>= 1;
-  const size_t lds_bytes = sizeof(uint32_t) * lds_words * (size_t)apb;
+  const size_t lds_bytes =
+      sizeof(uint32_t) * ((size_t)faco_team_lds_words(tw) + lds_words * (size_t)apb);
   // the tables are shared: the previous batch must be done with them
   if (!g_ws.last_done) BT(hipEventCreateWithFlags(&g_ws.last_done, hipEventDisableTiming));
   const bool grow = g_ws.cap_insts < (size_t)count || g_ws.cap_amap < (size_t)total;
   if (grow) BT(hipEventSynchronize(g_ws.last_done));
   BT(hipStreamWaitEvent(st, g_ws.last_done, 0));
   // device tables
+  std::unique_lock<std::mutex> alloc_lk(g_capture_mu);
   if (g_ws.cap_insts < (size_t)count) {
     if (g_ws.insts) (void)hipFree(g_ws.insts);
     g_ws.insts = nullptr;
@@ -517,6 +541,7 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
     BT(hipMalloc((void **)&g_ws.amap, sizeof(int2) * (size_t)total));
     g_ws.cap_amap = (size_t)total;
   }
+  alloc_lk.unlock();
   // order after the handles' own streams
   for (int32_t i = 0; i < count; ++i) {
     if (hs[i]->stream == st) continue;
@@ -530,15 +555,15 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
                     hipMemcpyHostToDevice, st));
   BT(hipMemcpyAsync(g_ws.amap, amap.data(), sizeof(int2) * (size_t)total,
                     hipMemcpyHostToDevice, st));
-  AntBatchFn antk = faco_ant_batch_kernel(kmax);
+  AntBatchFn antk = faco_ant_batch_kernel(kmax, tw);
   BT(hipFuncSetAttribute((const void *)antk, hipFuncAttributeMaxDynamicSharedMemorySize,
                          (int)lds_bytes));
   const unsigned nb_ant = (unsigned)((total + apb - 1) / apb);
   const dim3 g_src((unsigned)((maxn + 255) / 256), (unsigned)count);
   const dim3 g_tau((unsigned)((max_slots + 255) / 256), (unsigned)count);
   auto enqueue = [&](hipStream_t s) {
-    hipLaunchKernelGGL(antk, dim3(nb_ant), dim3(64 * apb), lds_bytes, s, g_ws.insts, g_ws.amap,
-                       total, apb, (int)lds_words);
+    hipLaunchKernelGGL(antk, dim3(nb_ant), dim3(64 * (tw > 1 ? tw : apb)), lds_bytes, s,
+                       g_ws.insts, g_ws.amap, total, apb, (int)lds_words);
     hipLaunchKernelGGL(faco::colony_batch_kernel, dim3((unsigned)count), dim3(64), 0, s,
                        (const Inst *)g_ws.insts);
     hipLaunchKernelGGL(faco::source_batch_kernel, g_src, dim3(256), 0, s,
@@ -555,9 +580,12 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
     BT(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t graph;
     hipGraphExec_t exec;
-    BT(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    enqueue(cap);
-    BT(hipStreamEndCapture(cap, &graph));
+    {
+      std::lock_guard<std::mutex> lk(g_capture_mu);
+      BT(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      enqueue(cap);
+      BT(hipStreamEndCapture(cap, &graph));
+    }
     BT(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     for (int32_t it = 0; it < iterations; ++it) BT(hipGraphLaunch(exec, st));
     BT(hipGraphExecDestroy(exec));

@@ -1542,11 +1542,18 @@ __global__ void __launch_bounds__(64 * TW) ant_kernel(Inst I, int mode) {
 // it would alone.
 //   insts  Inst [count]
 //   amap   int2 [total ants]: (instance, ant) of wave w = block * apb + wave
+//          (TW > 1: of block w, whose TW waves form the ant's team)
 // ===================================================================== //
-template <int KT>
-__global__ void __launch_bounds__(256) ant_batch_kernel(const Inst *insts, const int2 *amap,
-                                                       int total, int apb, int lds_words) {
+template <int KT, int TW>
+__global__ void __launch_bounds__(TW > 1 ? 64 * TW : 256)
+    ant_batch_kernel(const Inst *insts, const int2 *amap, int total, int apb, int lds_words) {
   extern __shared__ uint32_t lds[];
+  if (TW > 1) {
+    // one workgroup of TW waves per ant
+    const int2 m = amap[blockIdx.x];
+    run_ant<KT, TW>(insts[m.x], m.y, 0, lds);
+    return;
+  }
   const int wave = (int)(threadIdx.x / kWave);
   const int w = (int)blockIdx.x * apb + wave;
   if (w >= total) return;

@@ -56,6 +56,28 @@ def test_batch_equals_solo(apb):
         g.close()
 
 
+@pytest.mark.parametrize("tw", [4, 8])
+def test_team_batch_equals_solo(tw):
+    """Batched launches with a workgroup of tw waves per ant, on instances
+    long enough for team rewrites."""
+    ws = I.batch_instances(count=4, seed0=4100, n_lo=2500, n_hi=7000)
+    say(f"[gpu] team batch tw={tw} sizes={[w.n for w in ws]}")
+    F.faco_set_team_waves(tw)
+    try:
+        batch = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+        F.faco_run_batch(batch, 1)
+        F.faco_run_batch(batch, 3)
+    finally:
+        F.faco_set_team_waves(0)
+    solo = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    for g in solo:
+        F.faco_run_iterations(g, 4)
+    for w, gb, gs in zip(ws, batch, solo):
+        assert _same(_state(gb), _state(gs)), w.name
+    for g in batch + solo:
+        g.close()
+
+
 def test_batch_matches_oracle():
     ws = _batch_workloads(6)
     say(f"[gpu] batch vs oracle sizes={[w.n for w in ws]}")

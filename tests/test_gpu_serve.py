@@ -61,3 +61,42 @@ def test_request_larger_than_budget_is_rejected():
     with pytest.raises(F.FacoError):
         fut.result(timeout=60)
     srv.close()
+
+
+def test_capture_alongside_other_threads():
+    """A batch graph captured on one thread while another thread builds,
+    reads back and releases instances (the served pattern): no call may trip
+    over the capture."""
+    import threading
+    import torch
+    from paper_2203_02228_amd import instances as I
+    say("[gpu] capture alongside builds, reads and releases")
+    ws = I.batch_instances(count=4, seed0=4300, n_hi=1500)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    batch = [F.faco_build_instance(w.points(), stream=s1, **w.params()) for w in ws]
+    errors = []
+
+    def runner():
+        try:
+            for _ in range(12):
+                F.faco_run_batch(batch, 5, stream=s1)
+                s1.synchronize()
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    def churn():
+        try:
+            for i in range(12):
+                w = ws[i % len(ws)]
+                g = F.faco_build_instance(w.points(), stream=s2, **w.params())
+                F.faco_get_best_tour(g)
+                F.faco_debug_get(g, F.FACO_DBG_INFO)
+                g.close()
+        except Exception as e:
+            errors.append(repr(e))
+
+    ta, tb = threading.Thread(target=runner), threading.Thread(target=churn)
+    ta.start(); tb.start(); ta.join(); tb.join()
+    for g in batch:
+        g.close()
+    assert not errors, errors[:3]
