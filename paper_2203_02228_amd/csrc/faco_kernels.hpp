@@ -967,21 +967,24 @@ constexpr int kChunks = 16;  // 64-element chunks in flight per wave and round
 // Rewrites of more pairs than this (elements, for block moves: twice this)
 // are shared by the team; shorter ones are the leader's alone.
 constexpr int kTeamMinPairs = 256;
+// In a team each wave keeps fewer chunks in flight (the team supplies the
+// rest), which leaves registers for the ant's other state.
+constexpr int kTeamChunks = 8;
 
 // Reverse the cyclic array range of length L starting at s: pairs (i,
 // L-1-i) are disjoint, so the 64-pair chunks are dealt to the waves of a
-// team of TW in turn (chunk c to wave c mod TW), kChunks per wave in flight.
-template <int TW>
+// team of TW in turn (chunk c to wave c mod TW), CH per wave in flight.
+template <int TW, int CH = kChunks>
 FACO_DEV void reverse_part(int n, int s, int L, int w, int32_t *route, int32_t *pos,
                            int2 *rxy) {
   const int lane = lane_id();
   const int half = L >> 1;
   const int nch = (half + kWave - 1) / kWave;
-  for (int c0 = w; c0 < nch; c0 += TW * kChunks) {
-    int p1[kChunks], p2[kChunks], v1[kChunks], v2[kChunks];
-    int c1x[kChunks], c1y[kChunks], c2x[kChunks], c2y[kChunks];
+  for (int c0 = w; c0 < nch; c0 += TW * CH) {
+    int p1[CH], p2[CH], v1[CH], v2[CH];
+    int c1x[CH], c1y[CH], c2x[CH], c2y[CH];
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int i = (c0 + c * TW) * kWave + lane;
       if (i < half) {
         p1[c] = wrap1(s + i, n);
@@ -994,7 +997,7 @@ FACO_DEV void reverse_part(int n, int s, int L, int w, int32_t *route, int32_t *
       }
     }
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int i = (c0 + c * TW) * kWave + lane;
       if (i < half) {
         route[p1[c]] = v2[c];
@@ -1010,21 +1013,21 @@ FACO_DEV void reverse_part(int n, int s, int L, int w, int32_t *route, int32_t *
 
 // Move the cyclic block of D elements at src to dst = src -+ L (L <= 3,
 // D + L < n), keeping its order.  down: dst below src, rounds ascend; else
-// rounds descend.  A round reads TW * kChunks * 64 elements, then (after a
+// rounds descend.  A round reads TW * CH * 64 elements, then (after a
 // barrier when TW > 1) writes them: no round reads what a later-starting
 // write of another wave could clobber.
-template <int TW>
+template <int TW, int CH = kChunks>
 FACO_DEV void shift_part(int n, int src, int dst, int D, bool down, int w, int32_t *route,
                          int32_t *pos, int2 *rxy) {
   const int lane = lane_id();
-  constexpr int R = TW * kChunks * kWave;
+  constexpr int R = TW * CH * kWave;
   const int nr = (D + R - 1) / R;
   for (int r = 0; r < nr; ++r) {
     // round r covers elements [rb, rb + R); its chunks go to the waves in turn
     const int rb = (down ? r : nr - 1 - r) * R;
-    int v[kChunks], cvx[kChunks], cvy[kChunks];
+    int v[CH], cvx[CH], cvy[CH];
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int i = rb + (w + c * TW) * kWave + lane;
       if (i < D) {
         const int sp = wrap1(src + i, n);
@@ -1035,7 +1038,7 @@ FACO_DEV void shift_part(int n, int src, int dst, int D, bool down, int w, int32
     }
     if (TW > 1) team_sync();
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int i = rb + (w + c * TW) * kWave + lane;
       if (i < D) {
         const int d = wrap1(dst + i, n);
@@ -1053,8 +1056,11 @@ FACO_DEV void team_reverse(int n, int s, int L, TeamLds *tl, int32_t *route, int
                            int2 *rxy) {
   if (TW > 1 && (L >> 1) > kTeamMinPairs) {
     team_post(tl, OP_REVERSE, s, L);
-    reverse_part<TW>(n, s, L, 0, route, pos, rxy);
+    reverse_part<TW, kTeamChunks>(n, s, L, 0, route, pos, rxy);
     team_sync();
+  } else if (TW > 1) {
+    reverse_part<1, kTeamMinPairs / kWave>(n, s, L, 0, route, pos, rxy);
+    wave_fence();
   } else {
     reverse_part<1>(n, s, L, 0, route, pos, rxy);
     wave_fence();
@@ -1065,8 +1071,11 @@ FACO_DEV void team_shift(int n, int src, int dst, int D, bool down, TeamLds *tl,
                          int32_t *route, int32_t *pos, int2 *rxy) {
   if (TW > 1 && D > 2 * kTeamMinPairs) {
     team_post(tl, OP_SHIFT, src, dst, D, down ? 1 : 0);
-    shift_part<TW>(n, src, dst, D, down, 0, route, pos, rxy);
+    shift_part<TW, kTeamChunks>(n, src, dst, D, down, 0, route, pos, rxy);
     team_sync();
+  } else if (TW > 1) {
+    shift_part<1, 2 * kTeamMinPairs / kWave>(n, src, dst, D, down, 0, route, pos, rxy);
+    wave_fence();
   } else {
     shift_part<1>(n, src, dst, D, down, 0, route, pos, rxy);
     wave_fence();
@@ -1395,10 +1404,10 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
     const int op = uniform_i(tl->op);
     if (op == OP_EXIT) break;
     if (op == OP_REVERSE) {
-      reverse_part<TW>(I.n, team_arg(tl, 0), team_arg(tl, 1), w, route, pos, rxy);
+      reverse_part<TW, kTeamChunks>(I.n, team_arg(tl, 0), team_arg(tl, 1), w, route, pos, rxy);
     } else if (op == OP_SHIFT) {
-      shift_part<TW>(I.n, team_arg(tl, 0), team_arg(tl, 1), team_arg(tl, 2),
-                     team_arg(tl, 3) != 0, w, route, pos, rxy);
+      shift_part<TW, kTeamChunks>(I.n, team_arg(tl, 0), team_arg(tl, 1), team_arg(tl, 2),
+                                  team_arg(tl, 3) != 0, w, route, pos, rxy);
     } else if (op == OP_WINDOW) {
       WinOut o;
       window_part<KT, TW>(I, uniform_u64(tl->arg64[0]), (uint64_t)ant,
