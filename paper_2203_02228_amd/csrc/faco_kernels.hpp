@@ -1181,17 +1181,55 @@ FACO_DEV void q_spill(Queue &Q, int n) {
   Q.in_lds = 0;
 }
 
-FACO_DEV void push(int n, int x, Queue &Q, uint32_t *inq, uint32_t *touched) {
-  if (!uniform_i(bit_get(inq, x) ? 1 : 0)) {
-    if (Q.in_lds && Q.count == Q.cap) q_spill(Q, n);
-    if (lane_id() == 0) {
-      bit_set(inq, x);
-      bit_set(touched, x);
-      (Q.in_lds ? Q.lr : Q.gr)[Q.tail] = x;
-    }
-    Q.tail = Q.tail + 1 == Q.cap ? 0 : Q.tail + 1;
-    Q.count++;
+// push() of the cities x of the lanes with `take`, in lane order, all at once
+// (the cities are distinct).
+FACO_DEV int push_lanes(int n, int x, bool take, Queue &Q, uint32_t *inq, uint32_t *touched) {
+  const int lane = lane_id();
+  take = take && !bit_get(inq, x);
+  const uint64_t pm = ballot(take);
+  const int np = __builtin_popcountll(pm);
+  if (np == 0) return 0;
+  if (Q.in_lds && Q.count + np > Q.cap) q_spill(Q, n);
+  if (take) {
+    int t = Q.tail + __builtin_popcountll(pm & ((1ull << lane) - 1ull));
+    t = t >= Q.cap ? t - Q.cap : t;
+    bit_set(inq, x);
+    bit_set(touched, x);
+    (Q.in_lds ? Q.lr : Q.gr)[t] = x;
   }
+  if (!Q.in_lds) wave_fence();  // the global ring is read back by lane 0
+  Q.tail = Q.tail + np >= Q.cap ? Q.tail + np - Q.cap : Q.tail + np;
+  Q.count += np;
+  return np;
+}
+
+// push() of c[0], c[1], ... in that order, all at once: lane i takes c[i];
+// it is listed unless it already is or an earlier lane holds the same city,
+// and goes to the tail plus the number of listed lanes before it.
+template <int NP>
+FACO_DEV void push_all(int n, const int *c, Queue &Q, uint32_t *inq, uint32_t *touched) {
+  const int lane = lane_id();
+  int x = 0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) x = lane == i ? c[i] : x;
+  bool take = lane < NP && !bit_get(inq, x);
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+    if (i < lane && c[i] == x) take = false;
+  const uint64_t pm = ballot(take);
+  const int np = __builtin_popcountll(pm);
+  if (np == 0) return;
+  if (Q.in_lds && Q.count + np > Q.cap) q_spill(Q, n);
+  if (take) {
+    int t = Q.tail + __builtin_popcountll(pm & ((1ull << lane) - 1ull));
+    t = t >= Q.cap ? t - Q.cap : t;
+    bit_set(inq, x);
+    bit_set(touched, x);
+    (Q.in_lds ? Q.lr : Q.gr)[t] = x;
+  }
+  if (!Q.in_lds) wave_fence();  // the global ring is read back by lane 0
+  Q.tail = Q.tail + np >= Q.cap ? Q.tail + np - Q.cap : Q.tail + np;
+  Q.count += np;
 }
 
 // Sweep: test every touched city (ascending id) and list the improvable ones.
@@ -1219,13 +1257,8 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
     if (TW == 1) {
       bool f = false;
       if (lane < cnt) f = has_improving<KT>(I, flags, bx, route, pos, rxy);
-      uint64_t m = ballot(f);
-      while (m) {
-        const int l = ctz64(m);
-        m &= m - 1;
-        push(I.n, readlane_i(bx, l), Q, inq, touched);
-        ++pushed;
-      }
+      pushed += __builtin_popcountll(ballot(f));
+      push_lanes(I.n, bx, f, Q, inq, touched);
       return;
     }
     // cnt cities sit in tl->cities[0..cnt)
@@ -1234,13 +1267,9 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
     team_sync();
     for (int j = 0; j * kWave < cnt; ++j) {
       const int c = tl->cities[j * kWave + lane];
-      uint64_t m = uniform_u64(tl->mask[j]);
-      while (m) {
-        const int l = ctz64(m);
-        m &= m - 1;
-        push(I.n, readlane_i(c, l), Q, inq, touched);
-        ++pushed;
-      }
+      const uint64_t m = uniform_u64(tl->mask[j]);
+      pushed += __builtin_popcountll(m);
+      push_lanes(I.n, c, ((m >> lane) & 1ull) != 0, Q, inq, touched);
     }
   };
   for (int w0 = 0; w0 < W; w0 += kWave) {
@@ -1350,10 +1379,8 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       if (uniform_i(mv.kind) == 1) {
         cnt[CNT_MOVED_ELEMS] += apply_2opt<TW>(n, uniform_i(mv.px), uniform_i(mv.py),
                                                uniform_i(mv.pz), tl, route, pos, rxy);
-        push(n, mv.w, Q, inq, touched);
-        push(n, mv.x, Q, inq, touched);
-        push(n, mv.y, Q, inq, touched);
-        push(n, mv.z, Q, inq, touched);
+        const int pc[4] = {mv.w, mv.x, mv.y, mv.z};
+        push_all<4>(n, pc, Q, inq, touched);
         cnt[CNT_MOVES_2OPT]++;
       } else {
         cnt[CNT_MOVED_ELEMS] +=
@@ -1361,12 +1388,8 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                             uniform_i(mv.pb), uniform_i(mv.fpos), uniform_i(mv.pq),
                             uniform_i(mv.pp), mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2, tl,
                             route, pos, rxy);
-        push(n, mv.p, Q, inq, touched);
-        push(n, mv.q, Q, inq, touched);
-        push(n, mv.b, Q, inq, touched);
-        push(n, mv.e, Q, inq, touched);
-        push(n, mv.f, Q, inq, touched);
-        push(n, mv.l, Q, inq, touched);
+        const int pc[6] = {mv.p, mv.q, mv.b, mv.e, mv.f, mv.l};
+        push_all<6>(n, pc, Q, inq, touched);
         cnt[CNT_MOVES_OROPT]++;
       }
       tk[2] += ticks() - t1;
