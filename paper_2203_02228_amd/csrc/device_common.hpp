@@ -37,35 +37,67 @@ FACO_DEV int64_t shfl_xor_i64(int64_t v, int m) {
   int hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
-FACO_DEV int64_t wave_max_i64(int64_t v) {
-  for (int m = 32; m >= 1; m >>= 1) {
-    int64_t o = shfl_xor_i64(v, m);
-    v = o > v ? o : v;
-  }
+// Data-parallel-primitive (DPP) moves within rows of 16 lanes: the quad
+// permutations [1,0,3,2] and [2,3,0,1], the half-row mirror (lane i <-> 7-i)
+// and the row mirror (i <-> 15-i).  Applied in that order with a combining
+// operation they leave every lane of a row holding the row's combination.
+constexpr int kDppQuad1032 = 0xB1;
+constexpr int kDppQuad2301 = 0x4E;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+template <int CTRL>
+FACO_DEV int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+FACO_DEV int64_t dpp_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)dpp_i<CTRL>((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)dpp_i<CTRL>((int)(uint32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+struct OpMax { template <class T> FACO_DEV T operator()(T a, T b) const { return a > b ? a : b; } };
+struct OpMin { template <class T> FACO_DEV T operator()(T a, T b) const { return a < b ? a : b; } };
+struct OpAdd { template <class T> FACO_DEV T operator()(T a, T b) const { return a + b; } };
+
+template <class Op>
+FACO_DEV int64_t row_reduce_i64(int64_t v, Op op) {
+  v = op(v, dpp_i64<kDppQuad1032>(v));
+  v = op(v, dpp_i64<kDppQuad2301>(v));
+  v = op(v, dpp_i64<kDppRowHalfMirror>(v));
+  v = op(v, dpp_i64<kDppRowMirror>(v));
   return v;
 }
-FACO_DEV int64_t wave_min_i64(int64_t v) {
-  for (int m = 32; m >= 1; m >>= 1) {
-    int64_t o = shfl_xor_i64(v, m);
-    v = o < v ? o : v;
-  }
+template <class Op>
+FACO_DEV int row_reduce_i32(int v, Op op) {
+  v = op(v, dpp_i<kDppQuad1032>(v));
+  v = op(v, dpp_i<kDppQuad2301>(v));
+  v = op(v, dpp_i<kDppRowHalfMirror>(v));
+  v = op(v, dpp_i<kDppRowMirror>(v));
   return v;
 }
-FACO_DEV int64_t wave_sum_i64(int64_t v) {
-  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_i64(v, m);
-  return v;
+// Whole-wave reductions: rows by DPP, then the four row results.  Every
+// lane must be active; the result is uniform.
+template <class Op>
+FACO_DEV int64_t wave_reduce_i64(int64_t v, Op op) {
+  v = row_reduce_i64(v, op);
+  const int64_t r0 = readlane_i64(v, 0), r1 = readlane_i64(v, 16);
+  const int64_t r2 = readlane_i64(v, 32), r3 = readlane_i64(v, 48);
+  return op(op(r0, r1), op(r2, r3));
 }
-FACO_DEV int wave_sum_i32(int v) {
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-  return v;
+template <class Op>
+FACO_DEV int wave_reduce_i32(int v, Op op) {
+  v = row_reduce_i32(v, op);
+  const int r0 = readlane_i(v, 0), r1 = readlane_i(v, 16);
+  const int r2 = readlane_i(v, 32), r3 = readlane_i(v, 48);
+  return op(op(r0, r1), op(r2, r3));
 }
-FACO_DEV int wave_min_i32(int v) {
-  for (int m = 32; m >= 1; m >>= 1) {
-    int o = __shfl_xor(v, m);
-    v = o < v ? o : v;
-  }
-  return v;
-}
+FACO_DEV int64_t wave_max_i64(int64_t v) { return wave_reduce_i64(v, OpMax()); }
+FACO_DEV int64_t wave_min_i64(int64_t v) { return wave_reduce_i64(v, OpMin()); }
+FACO_DEV int64_t wave_sum_i64(int64_t v) { return wave_reduce_i64(v, OpAdd()); }
+FACO_DEV int wave_sum_i32(int v) { return wave_reduce_i32(v, OpAdd()); }
+FACO_DEV int wave_min_i32(int v) { return wave_reduce_i32(v, OpMin()); }
 
 // A value every lane holds alike, moved to a scalar register: control flow
 // on it is a scalar branch (needed where a workgroup barrier follows).

@@ -686,11 +686,12 @@ FACO_DEV int or_lmax(const Inst &I) {
 
 FACO_DEV int2 shfl_i2(int2 v, int l) { return make_int2(__shfl(v.x, l), __shfl(v.y, l)); }
 
+// Maximum over the GS lanes of a group (GS = 16: one DPP row; 32: two).
 template <int GS>
 FACO_DEV int64_t group_max(int64_t v) {
-#pragma unroll
-  for (int m = GS / 2; m >= 1; m >>= 1) {
-    const int64_t o = shfl_xor_i64(v, m);
+  v = row_reduce_i64(v, OpMax());
+  if (GS == 32) {
+    const int64_t o = shfl_xor_i64(v, 16);
     v = o > v ? o : v;
   }
   return v;
