@@ -57,6 +57,20 @@ FACO_DEV int64_t dpp_i64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Lane j of each 16-lane row to the whole row (DPP row broadcast, CDNA3+).
+FACO_DEV int row_bcast(int v, int j) {
+  switch (j) {
+#define FACO_BC(J) \
+  case J:          \
+    return dpp_i<0x150 + J>(v);
+    FACO_BC(0) FACO_BC(1) FACO_BC(2) FACO_BC(3) FACO_BC(4) FACO_BC(5) FACO_BC(6) FACO_BC(7)
+    FACO_BC(8) FACO_BC(9) FACO_BC(10) FACO_BC(11) FACO_BC(12) FACO_BC(13) FACO_BC(14)
+    FACO_BC(15)
+#undef FACO_BC
+  }
+  return v;
+}
+
 struct OpMax { template <class T> FACO_DEV T operator()(T a, T b) const { return a > b ? a : b; } };
 struct OpMin { template <class T> FACO_DEV T operator()(T a, T b) const { return a < b ? a : b; } };
 struct OpAdd { template <class T> FACO_DEV T operator()(T a, T b) const { return a + b; } };

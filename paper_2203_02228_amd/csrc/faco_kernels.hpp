@@ -686,6 +686,17 @@ FACO_DEV int or_lmax(const Inst &I) {
 
 FACO_DEV int2 shfl_i2(int2 v, int l) { return make_int2(__shfl(v.x, l), __shfl(v.y, l)); }
 
+// Lane j (constant after unrolling) of the lane's group of GS lanes.
+template <int GS>
+FACO_DEV int grp_lane(int v, int j) {
+  if (GS == 16) return row_bcast(v, j);
+  return __shfl(v, (lane_id() & ~(GS - 1)) + j);
+}
+template <int GS>
+FACO_DEV int2 grp_lane2(int2 v, int j) {
+  return make_int2(grp_lane<GS>(v.x, j), grp_lane<GS>(v.y, j));
+}
+
 // Maximum over the GS lanes of a group (GS = 16: one DPP row; 32: two).
 template <int GS>
 FACO_DEV int64_t group_max(int64_t v) {
@@ -738,7 +749,7 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
   const int2 xbs = rxy[pbs], xbp = rxy[pbp];
   R.pa = pa; R.b = b; R.pb = pb; R.pbs = pbs; R.pbp = pbp; R.bs = bs; R.bp = bp;
   R.nb = nb; R.xa = xa; R.xnb = xnb; R.xb = xb; R.xbs = xbs; R.xbp = xbp; R.d_ab = d_ab;
-  const int2 xas = shfl_i2(xnb, gb + 4), xap = shfl_i2(xnb, gb + 2);
+  const int2 xas = grp_lane2<GS>(xnb, 4), xap = grp_lane2<GS>(xnb, 2);
   // Costs that depend only on the city's neighbourhood nb_0..nb_6 (tour
   // positions pa-3..pa+3), one per lane of the group: the tour edges
   // (nb_j, nb_j+1), j = 0..5, and the shortcuts (nb_2, nb_4), (nb_2, nb_5),
@@ -753,7 +764,7 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
   R.d_bp = cost(xbp, xb);
   R.key2 = 0;
   if (flags & LS_2OPT) {
-    const int d_as = __shfl(R.uc, gb + 3), d_ap = __shfl(R.uc, gb + 2);
+    const int d_as = grp_lane<GS>(R.uc, 3), d_ap = grp_lane<GS>(R.uc, 2);
     int g1 = 0, g2 = 0;
     if (act && d_as > d_ab) g1 = d_as + R.d_bs - d_ab - cost(xas, xbs);
     if (act && d_ap > d_ab) g2 = d_ap + R.d_bp - d_ab - cost(xap, xbp);
@@ -769,7 +780,6 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
 template <int GS>
 FACO_DEV void eval_group_oropt(const Inst &I, bool want, GroupEval &R) {
   const int n = I.n, K = I.k, lane = lane_id();
-  const int gb = lane & ~(GS - 1);
   const int s = lane & (GS - 1);
   const bool act = want && s < K;
   const int pa = R.pa, pb = R.pb, pbs = R.pbs, pbp = R.pbp, d_ab = R.d_ab;
@@ -779,13 +789,13 @@ FACO_DEV void eval_group_oropt(const Inst &I, bool want, GroupEval &R) {
   const int d_bs = R.d_bs, d_bp = R.d_bp;
   int u[11];
 #pragma unroll
-  for (int j = 0; j < 11; ++j) u[j] = __shfl(R.uc, gb + j);
+  for (int j = 0; j < 11; ++j) u[j] = grp_lane<GS>(R.uc, j);
 #pragma unroll
   for (int vi = 0; vi < kOrSlots; ++vi) {
     int dir, L, lf, ll, lp, lq;
     or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
     if (L > Lmax) continue;
-    const int2 xf = shfl_i2(xnb, gb + lf), xl = shfl_i2(xnb, gb + ll);
+    const int2 xf = grp_lane2<GS>(xnb, lf), xl = grp_lane2<GS>(xnb, ll);
     const int2 xo = dir == 0 ? xl : xf;
     const int fpos = dir == 0 ? pa : wrapn(pa - L + 1, n);
     // removal: (p, f) + (l, q) - (p, q); rem_a: the edge at a it removes
