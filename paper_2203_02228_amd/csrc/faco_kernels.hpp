@@ -805,14 +805,16 @@ FACO_DEV void eval_group_oropt(const Inst &I, bool want, GroupEval &R) {
     if (!act) continue;
     if (!(d_ab < rem_a)) continue;
     if (wrapn(pb - fpos, n) < L) continue;
-    if (wrapn(pbs - fpos, n) >= L) {
+    // costs are >= 0: a variant whose gain without the new edge's cost
+    // cannot beat lbest needs no cost
+    if (wrapn(pbs - fpos, n) >= L && g_rem + d_bs - d_ab > lbest) {
       const int g = g_rem + d_bs - d_ab - cost(xo, xbs);
       if (g > lbest) {
         lbest = g;
         lidx = (vi * K + s) * 2 + 0;
       }
     }
-    if (wrapn(pbp - fpos, n) >= L) {
+    if (wrapn(pbp - fpos, n) >= L && g_rem + d_bp - d_ab > lbest) {
       const int g = g_rem + d_bp - d_ab - cost(xo, xbp);
       if (g > lbest) {
         lbest = g;
@@ -958,12 +960,16 @@ FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
         if (!(d_xb < rem)) break;
         if (wrapn(pb[s] - fpos, n) < L) continue;
         const int pbs = pb[s] + 1 == n ? 0 : pb[s] + 1, pbp = pb[s] == 0 ? n - 1 : pb[s] - 1;
-        if (wrapn(pbs - fpos, n) >= L &&
-            g_rem + cost(XB(s), XBS(s)) - d_xb - cost(xo, XBS(s)) > 0)
-          return true;
-        if (wrapn(pbp - fpos, n) >= L &&
-            g_rem + cost(XB(s), XBP(s)) - d_xb - cost(xo, XBP(s)) > 0)
-          return true;
+        // costs are >= 0: no cost of the new edge is needed unless the rest
+        // of the gain is positive
+        if (wrapn(pbs - fpos, n) >= L) {
+          const int rest = g_rem + cost(XB(s), XBS(s)) - d_xb;
+          if (rest > 0 && rest - cost(xo, XBS(s)) > 0) return true;
+        }
+        if (wrapn(pbp - fpos, n) >= L) {
+          const int rest = g_rem + cost(XB(s), XBP(s)) - d_xb;
+          if (rest > 0 && rest - cost(xo, XBP(s)) > 0) return true;
+        }
       }
     }
   }
