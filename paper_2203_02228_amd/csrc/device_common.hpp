@@ -158,14 +158,16 @@ FACO_DEV uint64_t sqd_u64(int2 a, int2 b) {
   return (uint64_t)ax * ax + (uint64_t)ay * ay;
 }
 FACO_DEV int cost(int2 a, int2 b) {
-  // dx^2 + dy^2 < 2^47 is exact in binary64; the correctly rounded square
-  // root s' of d2 is within 2^-29.5 of s = sqrt(d2) < 2^23.5 and s' + 0.5 is
-  // within 2^-28.5 of s + 0.5, while s is at least 0.25 / (2 s + 1) > 2^-26.5
-  // away from any half-integer (d2 is an integer): the truncation of s' + 0.5
-  // is exactly nint(s).  Binary64 vector operations run at full rate.
+  // d2 = dx^2 + dy^2 < 2^47 is exact in binary64.  nint(sqrt(d2)) is the
+  // unique C >= 0 with C^2 - C < d2 <= C^2 + C (d2 = 0: C = 0), because
+  // sqrt(d2) is never a half-integer.  The hardware square root estimates
+  // it to far better than +-0.5, so its rounding r is C or a neighbour; the
+  // two tests below, exact in binary64 (r^2 + r < 2^48), settle which.
   const double dx = (double)(a.x - b.x), dy = (double)(a.y - b.y);
   const double d2 = dx * dx + dy * dy;
-  return (int)(__dsqrt_rn(d2) + 0.5);
+  const int r = (int)(__builtin_amdgcn_sqrt(d2) + 0.5);
+  const double rd = (double)r, rr = rd * rd;
+  return r + (d2 > rr + rd ? 1 : 0) - (r > 0 && d2 <= rr - rd ? 1 : 0);
 }
 
 // ----------------------------------------------------------- Philox4x64 ---

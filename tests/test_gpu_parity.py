@@ -151,3 +151,22 @@ def test_full_coordinate_range():
         F.faco_run_iterations(g, 1)
         _cmp_iter(o, g, it)
     g.close()
+
+
+@pytest.mark.parametrize("spacing", [1, 7])
+def test_integer_grid(spacing):
+    """A 32 x 32 integer grid: squared lengths hit r^2 + r and r^2 - r + 1
+    (the nint boundaries, e.g. sqrt(20) -> 4, sqrt(13) -> 4, sqrt(5) -> 2) and
+    distances tie massively (lists break ties by city id)."""
+    g1 = np.arange(32, dtype=np.int32) * spacing + 5
+    xy = np.stack(np.meshgrid(g1, g1, indexing="ij"), -1).reshape(-1, 2).astype(np.int32)
+    xy = xy[np.random.default_rng(spacing).permutation(len(xy))].copy()
+    params = dict(n_ants=6, min_new_edges=10, cl_size=10, bl_size=20)
+    say(f"[gpu] integer grid spacing={spacing}")
+    o, g = _pair(xy, **params)
+    _cmp_setup(o, g)
+    for it in range(1, 5):
+        o.run(1)
+        F.faco_run_iterations(g, 1)
+        _cmp_iter(o, g, it)
+    g.close()
