@@ -337,7 +337,7 @@ template <int KT, int TW>
 FACO_DEV void window_part(const Inst &I, uint64_t t, uint64_t ant, uint64_t step, int u,
                           int pu, int dir, int k, int maxw, int w, TeamLds *tl,
                           uint32_t *vis, int32_t *route, int32_t *pos, int2 *rxy, Draws &D,
-                          WinOut &o) {
+                          WinOut &o, int round = 0) {
   const int n = I.n, K = I.k, lane = lane_id();
   const int g = w * kWave + lane;
   o.v = -2;
@@ -405,9 +405,10 @@ FACO_DEV void window_part(const Inst &I, uint64_t t, uint64_t ant, uint64_t step
   const uint64_t mm = ballot(!match);
   int F = mm ? w * kWave + ctz64(mm) : TW * kWave;
   if (TW > 1) {
-    if (lane == 0) tl->f[w] = F;
+    int *f = tl->f + (round & 1) * kMaxTeam;
+    if (lane == 0) f[w] = F;
     team_sync();  // every wave's evaluation is done before any append
-    F = wave_min_i32(lane < TW ? tl->f[lane] : 0x7fffffff);
+    F = uniform_i(wave_min_i32(lane < TW ? f[lane] : 0x7fffffff));
   }
   const int acc = F < valid ? F : valid;
   if (g < acc) {
@@ -434,7 +435,7 @@ FACO_DEV void window_part(const Inst &I, uint64_t t, uint64_t ant, uint64_t step
     }
   } else {
     // results for the leader, read after the closing barrier
-    if (lane == 0) tl->part[w] = ssum;
+    o.srcsum = ssum;
     if (acc > 0 && g == acc - 1) tl->res[0] = qn;
     if (acc < valid && g == acc) {
       tl->res[1] = special ? -1 : choice;
@@ -443,6 +444,42 @@ FACO_DEV void window_part(const Inst &I, uint64_t t, uint64_t ant, uint64_t step
     }
     o.v = acc < valid ? 0 : -2;
   }
+}
+
+// A team runs up to kWinRounds windows in one command: while a window is
+// followed to its end, the next one starts from where it stopped (every wave
+// derives the new start alike; the last followed city comes through LDS).
+// Per-wave partial sums of the followed edges end in tl->part.
+constexpr int kWinRounds = 4;
+template <int KT, int TW>
+FACO_DEV void window_rounds(const Inst &I, uint64_t t, uint64_t ant, uint64_t step, int u,
+                            int pu, int dir, int k, int maxw, int w, TeamLds *tl,
+                            uint32_t *vis, int32_t *route, int32_t *pos, int2 *rxy, Draws &D,
+                            WinOut &o) {
+  const int n = I.n;
+  int total = 0;
+  int64_t sum = 0;
+  for (int r = 0;; ++r) {
+    WinOut q;
+    window_part<KT, TW>(I, t, ant, step, u, pu, dir, k, maxw, w, tl, vis, route, pos, rxy, D,
+                        q, r);
+    const int acc = uniform_i(q.acc);
+    total += acc;
+    sum += q.srcsum;
+    int valid = n - k < TW * kWave ? n - k : TW * kWave;
+    valid = valid < maxw ? valid : maxw;
+    team_sync();  // this window's appends and results are visible
+    if (acc < valid || r + 1 >= kWinRounds || k + acc >= n) {
+      o = q;
+      break;
+    }
+    u = uniform_i(tl->res[0]);
+    pu = wrap_off(pu, dir * acc, n);
+    k += acc;
+    step += (uint64_t)acc;
+  }
+  o.acc = total;
+  if (lane_id() == 0) tl->part[w] = sum;
 }
 
 // Leader side of a window (TW > 1: posts it, takes wave 0's share, collects).
@@ -458,8 +495,12 @@ FACO_DEV WinOut team_window(const Inst &I, uint64_t t, uint64_t ant, uint64_t st
     }
     team_post(tl, OP_WINDOW, u, pu, dir, k, maxw);
   }
-  window_part<KT, TW>(I, t, ant, step, u, pu, dir, k, maxw, 0, tl, vis, route, pos, rxy, D,
-                      o);
+  if (TW > 1)
+    window_rounds<KT, TW>(I, t, ant, step, u, pu, dir, k, maxw, 0, tl, vis, route, pos, rxy, D,
+                          o);
+  else
+    window_part<KT, TW>(I, t, ant, step, u, pu, dir, k, maxw, 0, tl, vis, route, pos, rxy, D,
+                        o);
   if (TW > 1) {
     team_sync();
     o.acc = uniform_i(o.acc);
@@ -1450,10 +1491,10 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
                                   team_arg(tl, 3) != 0, w, route, pos, rxy);
     } else if (op == OP_WINDOW) {
       WinOut o;
-      window_part<KT, TW>(I, uniform_u64(tl->arg64[0]), (uint64_t)ant,
-                          uniform_u64(tl->arg64[1]), team_arg(tl, 0), team_arg(tl, 1),
-                          team_arg(tl, 2), team_arg(tl, 3), team_arg(tl, 4), w, tl, vis,
-                          route, pos, rxy, D, o);
+      window_rounds<KT, TW>(I, uniform_u64(tl->arg64[0]), (uint64_t)ant,
+                            uniform_u64(tl->arg64[1]), team_arg(tl, 0), team_arg(tl, 1),
+                            team_arg(tl, 2), team_arg(tl, 3), team_arg(tl, 4), w, tl, vis,
+                            route, pos, rxy, D, o);
     } else if (op == OP_COPY) {
       CopyOut o;
       copy_rounds<TW>(I, team_arg(tl, 0), team_arg(tl, 1), team_arg(tl, 2), w, tl, vis, route,
