@@ -6,6 +6,7 @@
 // (a parameter of the trail-limit formula, Sec. 4.5) and marshals pointers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -35,6 +36,7 @@ struct faco_instance {
   std::string err;
   size_t lds_ant = 0;
   int tw = 1;  // waves per ant in the per-instance ant kernel
+  std::vector<int32_t> orig_of, int_of;  // internal label <-> original city number
   bool timing = false;
   std::vector<TimedLaunch> pending;
   double phase_ms[4] = {0, 0, 0, 0};
@@ -96,6 +98,7 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   b += 4 * align_up(4 * NB * (uint64_t)k);  // source-ordered city, weight, position, cost
   b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
   b += 4 * align_up(4 * N) + align_up(8 * N); // source route/pos/edge costs, adjacency, global best
+  b += 2 * align_up(4 * N);                   // label maps
   b += 3 * align_up(4 * N * A) + align_up(8 * N * A);  // ant routes, pos, rings, tour coordinates
   b += align_up(8 * A) + 2 * align_up(8 * A * faco::NCNT) + align_up(128 * A);
   b += align_up(sizeof(DevState));
@@ -122,7 +125,8 @@ static int dalloc(faco_instance *h, void **ptr, size_t bytes) {
 }
 
 static size_t knn_lds_bytes(int K, int BL) {
-  return sizeof(int2) * faco::kKnnTile + (sizeof(double) + sizeof(int32_t)) * (size_t)(K + BL) * 64;
+  return (sizeof(int2) + sizeof(int32_t)) * faco::kKnnTile +
+         (sizeof(double) + sizeof(int32_t)) * (size_t)(K + BL) * 64;
 }
 
 static void begin_timed(faco_instance *h, int phase, TimedLaunch &tl) {
@@ -160,9 +164,16 @@ extern "C" int faco_set_queue_lds_capacity(int32_t cap) {
   return FACO_OK;
 }
 
+// The queue ring takes what LDS is left next to the team area and three
+// n-bit bitmaps (160 KB per CU).
 static int queue_lds_cap_for(int32_t n) {
-  std::lock_guard<std::mutex> lk(g_team_mu);
-  return n < g_queue_lds_cap ? n : g_queue_lds_cap;
+  int cap;
+  {
+    std::lock_guard<std::mutex> lk(g_team_mu);
+    cap = n < g_queue_lds_cap ? n : g_queue_lds_cap;
+  }
+  const int room = 160 * 1024 / 4 - faco_team_lds_words(8) - 3 * ((n + 31) / 32);
+  return cap < room ? cap : room;
 }
 
 static int team_waves_for(int32_t n, int32_t ants) {
@@ -209,6 +220,54 @@ static int enqueue_iteration(faco_instance *h) {
   return FACO_OK;
 }
 
+// Internal labels: the cities in the order of a Hilbert curve over the
+// coordinates (16-bit cells over the bounding box; ties by original number).
+// A relabelling only: every rule that depends on city numbers uses the
+// original ones, so results do not change.
+static uint64_t hilbert_d(uint32_t x, uint32_t y) {
+  const uint32_t side = 1u << 16;
+  uint64_t d = 0;
+  for (uint32_t s = side >> 1; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += (uint64_t)s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = side - 1 - x;
+        y = side - 1 - y;
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
+}
+
+static void hilbert_labels(const int32_t *xy, int32_t n, std::vector<int32_t> &orig_of,
+                           std::vector<int32_t> &int_of) {
+  int64_t x0 = xy[0], x1 = xy[0], y0 = xy[1], y1 = xy[1];
+  for (int32_t i = 1; i < n; ++i) {
+    x0 = std::min<int64_t>(x0, xy[2 * i]);
+    x1 = std::max<int64_t>(x1, xy[2 * i]);
+    y0 = std::min<int64_t>(y0, xy[2 * i + 1]);
+    y1 = std::max<int64_t>(y1, xy[2 * i + 1]);
+  }
+  const int64_t span = std::max<int64_t>(1, std::max(x1 - x0, y1 - y0));
+  std::vector<std::pair<uint64_t, int32_t>> key((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    const uint32_t gx = (uint32_t)((xy[2 * i] - x0) * 65535 / span);
+    const uint32_t gy = (uint32_t)((xy[2 * i + 1] - y0) * 65535 / span);
+    key[(size_t)i] = {hilbert_d(gx, gy), i};
+  }
+  std::sort(key.begin(), key.end());
+  orig_of.resize((size_t)n);
+  int_of.resize((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    orig_of[(size_t)i] = key[(size_t)i].second;
+    int_of[(size_t)key[(size_t)i].second] = i;
+  }
+}
+
 extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_params *p,
                                    void *hip_stream, faco_instance **out) {
   if (!out) return set_err(nullptr, FACO_EINVAL, "out is NULL");
@@ -251,6 +310,8 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   }                                                    \
   I.field = (type *)ptr;
   ALLOC(xy, int2, N);
+  ALLOC(orig_of, int32_t, N);
+  ALLOC(int_of, int32_t, N);
   ALLOC(cl, int32_t, N * K);
   ALLOC(bll, int32_t, N * BL + 1);
   ALLOC(eta, float, N * K);
@@ -291,13 +352,25 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   BTRY(hipMemsetAsync(I.st, 0, sizeof(DevState), h->stream));
   BTRY(hipMemsetAsync(I.cnt_acc, 0, sizeof(int64_t) * A * faco::NCNT, h->stream));
   BTRY(hipMemsetAsync(I.ticks, 0, sizeof(int64_t) * A * 16, h->stream));
-  BTRY(hipMemcpyAsync((void *)I.xy, xy, sizeof(int2) * N, hipMemcpyHostToDevice, h->stream));
+  hilbert_labels(xy, n, h->orig_of, h->int_of);
+  std::vector<int32_t> xy_int(2 * N);
+  for (size_t i = 0; i < N; ++i) {
+    xy_int[2 * i] = xy[2 * (size_t)h->orig_of[i]];
+    xy_int[2 * i + 1] = xy[2 * (size_t)h->orig_of[i] + 1];
+  }
+  BTRY(hipMemcpyAsync((void *)I.xy, xy_int.data(), sizeof(int2) * N, hipMemcpyHostToDevice,
+                      h->stream));
+  BTRY(hipMemcpyAsync((void *)I.orig_of, h->orig_of.data(), sizeof(int32_t) * N,
+                      hipMemcpyHostToDevice, h->stream));
+  BTRY(hipMemcpyAsync((void *)I.int_of, h->int_of.data(), sizeof(int32_t) * N,
+                      hipMemcpyHostToDevice, h->stream));
 
   const size_t klds = knn_lds_bytes(h->k, h->bl);
   BTRY(hipFuncSetAttribute((const void *)faco::knn_kernel,
                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)klds));
   hipLaunchKernelGGL(faco::knn_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), klds,
-                     h->stream, I.xy, n, h->k, h->bl, (int32_t *)I.cl, (int32_t *)I.bll,
+                     h->stream, I.xy, I.orig_of, I.int_of, n, h->k, h->bl, (int32_t *)I.cl,
+                     (int32_t *)I.bll,
                      (float *)I.eta, (int32_t *)I.cl_d, I.st);
   BTRY(hipGetLastError());
   DevState hs;
@@ -310,8 +383,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
 
   h->tw = team_waves_for(n, p->n_ants);
   h->lds_ant = sizeof(uint32_t) * ((size_t)faco_team_lds_words(h->tw) +
-                                   2 * (size_t)((n + 31) / 32) +
-                                   (size_t)I.lcap);
+                                   3 * (size_t)((n + 31) / 32) + (size_t)I.lcap);
   BTRY(hipFuncSetAttribute((const void *)faco_ant_kernel(h->k, h->tw),
                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_ant));
   // initial solution (ant slot 0), limits, tau = tau_max, source = global best
@@ -351,8 +423,10 @@ static hipError_t d2h(faco_instance *h, void *dst, const void *src, size_t bytes
 extern "C" int faco_get_best_tour(faco_instance *h, int32_t *tour_out, int64_t *length_out) {
   if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  if (tour_out)
+  if (tour_out) {
     HIP_TRY(h, d2h(h, tour_out, h->dv.gb_route, sizeof(int32_t) * (size_t)h->n));
+    for (int32_t i = 0; i < h->n; ++i) tour_out[i] = h->orig_of[(size_t)tour_out[i]];
+  }
   if (length_out) {
     DevState hs;
     HIP_TRY(h, d2h(h, &hs, h->dv.st, sizeof(DevState)));
@@ -426,6 +500,32 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
   }
   if (bytes != need) return set_err(h, FACO_EINVAL, "size mismatch");
   if (need) HIP_TRY(h, d2h(h, out, src, need));
+  // back to original city numbers: city values, and rows indexed by city
+  const auto &orig = h->orig_of;
+  auto map_values = [&](int32_t *v, size_t cnt) {
+    for (size_t i = 0; i < cnt; ++i) v[i] = orig[(size_t)v[i]];
+  };
+  auto permute_rows = [&](void *base, size_t row_bytes) {
+    std::vector<unsigned char> tmp((unsigned char *)base, (unsigned char *)base + N * row_bytes);
+    for (size_t i = 0; i < N; ++i)
+      std::memcpy((unsigned char *)base + (size_t)orig[i] * row_bytes, tmp.data() + i * row_bytes,
+                  row_bytes);
+  };
+  switch (what) {
+    case FACO_DBG_ANT_ROUTES: map_values((int32_t *)out, N * A); break;
+    case FACO_DBG_SOURCE: map_values((int32_t *)out, N); break;
+    case FACO_DBG_PHEROMONE:
+    case FACO_DBG_HEURISTIC: permute_rows(out, 4 * K); break;
+    case FACO_DBG_CAND_LISTS:
+      map_values((int32_t *)out, N * K);
+      permute_rows(out, 4 * K);
+      break;
+    case FACO_DBG_BACKUP_LISTS:
+      map_values((int32_t *)out, N * BL);
+      if (BL) permute_rows(out, 4 * BL);
+      break;
+    default: break;
+  }
   return FACO_OK;
 }
 
@@ -507,7 +607,7 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
     insts[i] = h->dv;
     kmax = h->k > kmax ? h->k : kmax;
     maxn = h->n > maxn ? h->n : maxn;
-    const size_t words = 2 * (size_t)((h->n + 31) / 32) + (size_t)h->dv.lcap;
+    const size_t words = 3 * (size_t)((h->n + 31) / 32) + (size_t)h->dv.lcap;
     lds_words = words > lds_words ? words : lds_words;
     const size_t slots = (size_t)h->n * (size_t)h->k;
     max_slots = slots > max_slots ? slots : max_slots;

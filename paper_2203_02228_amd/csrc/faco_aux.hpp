@@ -159,58 +159,70 @@ __global__ void __launch_bounds__(256) pheromone_batch_kernel(const Inst *insts)
 
 // ===================================================================== //
 // Candidate + backup lists (Sec. 4.1): the K + BL nearest cities by
-// (squared distance, id); eta = 1/d.  One query city per lane; candidate
+// (squared distance, original number); eta = 1/d.  One query city per lane; candidate
 // cities stream through LDS in tiles; each lane keeps its sorted list in LDS.
 // ===================================================================== //
 constexpr int kKnnTile = 256;
 
-__global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, int n, int K, int BL,
-                                                 int32_t *cl, int32_t *bll, float *eta,
-                                                 int32_t *cl_d, DevState *st) {
+__global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, const int32_t *orig_of,
+                                                 const int32_t *int_of, int n,
+                                                 int K, int BL, int32_t *cl, int32_t *bll,
+                                                 float *eta, int32_t *cl_d, DevState *st) {
   extern __shared__ unsigned char knn_lds[];
   const int KK = K + BL;
   const int tid = threadIdx.x;
   int2 *tile = reinterpret_cast<int2 *>(knn_lds);
-  double *kd = reinterpret_cast<double *>(knn_lds + sizeof(int2) * kKnnTile);
-  int32_t *kj = reinterpret_cast<int32_t *>(knn_lds + sizeof(int2) * kKnnTile +
+  int32_t *tile_o = reinterpret_cast<int32_t *>(knn_lds + sizeof(int2) * kKnnTile);
+  double *kd = reinterpret_cast<double *>(knn_lds + (sizeof(int2) + sizeof(int32_t)) * kKnnTile);
+  int32_t *ko = reinterpret_cast<int32_t *>(knn_lds + (sizeof(int2) + sizeof(int32_t)) * kKnnTile +
                                             sizeof(double) * (size_t)KK * 64);
   const int i = blockIdx.x * 64 + tid;
   const bool valid = i < n;
   const int2 xi = valid ? xy[i] : make_int2(0, 0);
+  const int oi = valid ? orig_of[i] : -1;
   int cnt = 0;
   double worst = 0.0;
+  int worst_o = 0;
   for (int t0 = 0; t0 < n; t0 += kKnnTile) {
     __syncthreads();
     for (int j = tid; j < kKnnTile; j += 64)
-      if (t0 + j < n) tile[j] = xy[t0 + j];
+      if (t0 + j < n) {
+        tile[j] = xy[t0 + j];
+        tile_o[j] = orig_of[t0 + j];
+      }
     __syncthreads();
     const int tn = min(kKnnTile, n - t0);
     if (!valid) continue;
     for (int jj = 0; jj < tn; ++jj) {
-      const int j = t0 + jj;
-      if (j == i) continue;
+      const int oj = tile_o[jj];
+      if (oj == oi) continue;
       const double d = sqd(xi, tile[jj]);
-      if (cnt == KK && !(d < worst)) continue;
+      // the list is sorted by (squared distance, original number)
+      if (cnt == KK && !(d < worst || (d == worst && oj < worst_o))) continue;
       int q = cnt < KK ? cnt++ : KK - 1;
-      while (q > 0 && kd[(q - 1) * 64 + tid] > d) {
+      while (q > 0 && (kd[(q - 1) * 64 + tid] > d ||
+                       (kd[(q - 1) * 64 + tid] == d && ko[(q - 1) * 64 + tid] > oj))) {
         kd[q * 64 + tid] = kd[(q - 1) * 64 + tid];
-        kj[q * 64 + tid] = kj[(q - 1) * 64 + tid];
+        ko[q * 64 + tid] = ko[(q - 1) * 64 + tid];
         --q;
       }
       kd[q * 64 + tid] = d;
-      kj[q * 64 + tid] = j;
-      if (cnt == KK) worst = kd[(KK - 1) * 64 + tid];
+      ko[q * 64 + tid] = oj;
+      if (cnt == KK) {
+        worst = kd[(KK - 1) * 64 + tid];
+        worst_o = ko[(KK - 1) * 64 + tid];
+      }
     }
   }
   if (!valid) return;
   for (int s = 0; s < K; ++s) {
     const double d2 = kd[s * 64 + tid];
-    cl[(size_t)i * K + s] = kj[s * 64 + tid];
+    cl[(size_t)i * K + s] = int_of[ko[s * 64 + tid]];
     const int d = (int)floor(sqrt(d2) + 0.5);
     cl_d[(size_t)i * K + s] = d;
     eta[(size_t)i * K + s] = (float)(1.0 / (double)d);
   }
-  for (int s = 0; s < BL; ++s) bll[(size_t)i * BL + s] = kj[(K + s) * 64 + tid];
+  for (int s = 0; s < BL; ++s) bll[(size_t)i * BL + s] = int_of[ko[(K + s) * 64 + tid]];
   if (kd[tid] == 0.0) atomicOr(&st->dup, 1);
 }
 

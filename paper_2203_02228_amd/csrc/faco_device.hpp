@@ -37,7 +37,13 @@ struct Inst {
   uint64_t seed;
   double p_gb;   // probability the source is the global best
   double p_root; // p_best^(1/n)
-  const int2 *xy;
+  // Cities are relabelled internally along a Hilbert curve of the
+  // coordinates (spatially close cities get close labels, so a tour segment's
+  // cities share cache lines).  Every rule that depends on a city's number
+  // uses its original number: orig_of[internal], int_of[original].
+  const int32_t *orig_of;
+  const int32_t *int_of;
+  const int2 *xy;     // [n] coordinates by internal label
   const int32_t *cl;
   const int32_t *bll;
   const float *eta;

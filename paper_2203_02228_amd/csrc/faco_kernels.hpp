@@ -53,7 +53,7 @@ FACO_DEV int wrap_off(int q, int off, int n) {
 constexpr int kMaxTeam = 8;
 enum TeamOp {
   OP_EXIT = 0, OP_REVERSE = 1, OP_SHIFT = 2, OP_WINDOW = 3, OP_SWEEP = 4, OP_COPY = 5,
-  OP_NEAREST = 6
+  OP_NEAREST = 6, OP_ORDMARK = 7
 };
 struct TeamLds {
   int op;
@@ -98,7 +98,7 @@ FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, Tea
   const int2 xu = I.xy[u];
   const int W = (I.n + 31) >> 5;
   int64_t bd = INT64_MAX;
-  int bj = 0x7fffffff;
+  int bo = 0x7fffffff, bj = 0x7fffffff;
   for (int wi = w * kWave + lane; wi < W; wi += TW * kWave) {
     uint32_t free_bits = ~vis[wi];
     const int rem = I.n - wi * 32;
@@ -107,17 +107,21 @@ FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, Tea
       const int j = wi * 32 + __builtin_ctz(free_bits);
       free_bits &= free_bits - 1;
       const int64_t d = (int64_t)sqd_u64(xu, I.xy[j]);
-      if (d < bd) {
+      const int o = I.orig_of[j];
+      if (d < bd || (d == bd && o < bo)) {
         bd = d;
+        bo = o;
         bj = j;
       }
     }
   }
   md = wave_min_i64(bd);
-  mj = wave_min_i32(bd == md ? bj : 0x7fffffff);
+  const int mo = wave_min_i32(bd == md ? bo : 0x7fffffff);
+  mj = wave_min_i32(bd == md && bo == mo ? bj : 0x7fffffff);
   if (TW > 1 && lane == 0) {
     tl->part[w] = md;
-    tl->f[w] = mj;
+    tl->f[w] = mo;
+    tl->f[kMaxTeam + w] = mj;
   }
 }
 
@@ -136,7 +140,7 @@ FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, TeamLds 
     cnt[CNT_BACKUP]++;
     return readlane_i(b, ctz64(bm));
   }
-  // best heuristic value = nearest unvisited city, ties by smaller id
+  // best heuristic value = nearest unvisited city, ties by smaller original number
   cnt[CNT_FALLBACK]++;
   int64_t md;
   int mj;
@@ -148,9 +152,11 @@ FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, TeamLds 
   nearest_part<TW>(I, u, 0, vis, tl, md, mj);
   team_sync();
   const int64_t d = lane < TW ? tl->part[lane] : INT64_MAX;
-  const int j = lane < TW ? tl->f[lane] : 0x7fffffff;
+  const int o = lane < TW ? tl->f[lane] : 0x7fffffff;
+  const int j = lane < TW ? tl->f[kMaxTeam + lane] : 0x7fffffff;
   const int64_t dmin = wave_min_i64(d);
-  return uniform_i(wave_min_i32(d == dmin ? j : 0x7fffffff));
+  const int omin = wave_min_i32(d == dmin ? o : 0x7fffffff);
+  return uniform_i(wave_min_i32(d == dmin && o == omin ? j : 0x7fffffff));
 }
 
 // Greedy step of the nearest-neighbour tour: first unvisited candidate
@@ -582,10 +588,11 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
     inq[w] = 0u;
   }
   wave_fence();
-  const int r0 = greedy ? 0
-                        : uniform_node(philox_word0(I.seed, t, (uint64_t)ant, 0,
-                                                    kPurposeStart),
-                                       n);
+  // start: city 0 for the greedy tour, else a uniform draw (original numbers)
+  const int r0 = uniform_i(
+      I.int_of[greedy ? 0
+                      : uniform_node(philox_word0(I.seed, t, (uint64_t)ant, 0, kPurposeStart),
+                                     n)]);
   int u = r0;
   append_city(I, u, 0, route, pos, rxy, vis);
   int k = 1, new_edges = 0;
@@ -1290,38 +1297,84 @@ FACO_DEV void push_all(int n, const int *c, Queue &Q, uint32_t *inq, uint32_t *t
   Q.count += np;
 }
 
-// Sweep: test every touched city (ascending id) and list the improvable ones.
-// Cities are tested 64 TW at a time (wave w of the team takes the w-th 64);
-// the improvable ones are listed in ascending id.
+// Sweep: test every touched city in ascending original number and list the
+// improvable ones.  First the touched cities' original numbers are marked
+// in the `ord` bitmap (wave w of a team takes the w-th share of the words);
+// then `ord` is read in ascending order, cities are tested 64 TW at a time
+// (wave w takes the w-th 64, translating original numbers back), and the
+// improvable ones are listed in that order.
+template <int TW>
+FACO_DEV void ord_mark_part(const Inst &I, int W, int w, const uint32_t *touched,
+                            uint32_t *ord) {
+  const int lane = lane_id();
+  const int w_lo = (int)((int64_t)W * w / TW), w_hi = (int)((int64_t)W * (w + 1) / TW);
+  int bx = 0, bcount = 0;
+  for (int w0 = w_lo; w0 < w_hi; w0 += kWave) {
+    const uint32_t word = (w0 + lane < w_hi) ? touched[w0 + lane] : 0u;
+    uint64_t nz = ballot(word != 0u);
+    while (nz) {
+      const int l = ctz64(nz);
+      nz &= nz - 1;
+      uint32_t bits = (uint32_t)readlane_i((int)word, l);
+      while (bits) {
+        const int bpos = __builtin_ctz(bits);
+        bits &= bits - 1;
+        if (lane == bcount) bx = (w0 + l) * 32 + bpos;
+        if (++bcount == kWave) {
+          bit_set(ord, I.orig_of[bx]);
+          bcount = 0;
+        }
+      }
+    }
+  }
+  if (lane < bcount) bit_set(ord, I.orig_of[bx]);
+}
+
 template <int KT, int TW>
-FACO_DEV void sweep_part(const Inst &I, uint32_t flags, int count, int w, const TeamLds *tl,
-                         const int32_t *route, const int32_t *pos, const int2 *rxy,
-                         TeamLds *out) {
+FACO_DEV void sweep_part(const Inst &I, uint32_t flags, int count, int w, TeamLds *tl,
+                         const int32_t *route, const int32_t *pos, const int2 *rxy) {
   const int i = w * kWave + lane_id();
   bool f = false;
-  if (i < count) f = has_improving<KT>(I, flags, tl->cities[i], route, pos, rxy);
+  if (i < count) {
+    const int x = I.int_of[tl->cities[i]];
+    tl->cities[i] = x;
+    f = has_improving<KT>(I, flags, x, route, pos, rxy);
+  }
   const uint64_t m = ballot(f);
-  if (lane_id() == 0) out->mask[w] = m;
+  if (lane_id() == 0) tl->mask[w] = m;
 }
 
 template <int KT, int TW>
 FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
                    const int32_t *route, const int32_t *pos, const int2 *rxy,
-                   uint32_t *inq, uint32_t *touched, TeamLds *tl) {
+                   uint32_t *inq, uint32_t *touched, uint32_t *ord, TeamLds *tl) {
   const int lane = lane_id();
   int pushed = 0;
-  int bx = -1, bcount = 0, nbuf = 0;
+  if (TW > 1) {
+    team_post(tl, OP_ORDMARK);
+    ord_mark_part<TW>(I, W, 0, touched, ord);
+    team_sync();
+  } else {
+    ord_mark_part<1>(I, W, 0, touched, ord);
+    wave_fence();
+  }
+  int bo = -1, bcount = 0, nbuf = 0;
   auto flush = [&](int cnt) {
     if (TW == 1) {
       bool f = false;
-      if (lane < cnt) f = has_improving<KT>(I, flags, bx, route, pos, rxy);
+      int x = 0;
+      if (lane < cnt) {
+        x = I.int_of[bo];
+        f = has_improving<KT>(I, flags, x, route, pos, rxy);
+      }
       pushed += __builtin_popcountll(ballot(f));
-      push_lanes(I.n, bx, f, Q, inq, touched);
+      push_lanes(I.n, x, f, Q, inq, touched);
       return;
     }
-    // cnt cities sit in tl->cities[0..cnt)
+    // cnt original numbers sit in tl->cities[0..cnt); the team translates
+    // them in place and tests them
     team_post(tl, OP_SWEEP, cnt, (int)flags);
-    sweep_part<KT, TW>(I, flags, cnt, 0, tl, route, pos, rxy, tl);
+    sweep_part<KT, TW>(I, flags, cnt, 0, tl, route, pos, rxy);
     team_sync();
     for (int j = 0; j * kWave < cnt; ++j) {
       const int c = tl->cities[j * kWave + lane];
@@ -1331,7 +1384,8 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
     }
   };
   for (int w0 = 0; w0 < W; w0 += kWave) {
-    const uint32_t word = (w0 + lane < W) ? touched[w0 + lane] : 0u;
+    const uint32_t word = (w0 + lane < W) ? ord[w0 + lane] : 0u;
+    if (w0 + lane < W) ord[w0 + lane] = 0u;  // left clear for the next sweep
     uint64_t nz = ballot(word != 0u);
     while (nz) {
       const int l = ctz64(nz);
@@ -1340,13 +1394,13 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
       while (bits) {
         const int bpos = __builtin_ctz(bits);
         bits &= bits - 1;
-        const int x = (w0 + l) * 32 + bpos;
-        if (lane == bcount) bx = x;
+        const int o = (w0 + l) * 32 + bpos;
+        if (lane == bcount) bo = o;
         if (++bcount == kWave) {
           if (TW == 1) {
             flush(kWave);
           } else {
-            tl->cities[nbuf * kWave + lane] = bx;
+            tl->cities[nbuf * kWave + lane] = bo;
             if (++nbuf == TW) {
               flush(TW * kWave);
               nbuf = 0;
@@ -1360,7 +1414,7 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
   if (TW == 1) {
     if (bcount) flush(bcount);
   } else {
-    if (bcount) tl->cities[nbuf * kWave + lane] = bx;
+    if (bcount) tl->cities[nbuf * kWave + lane] = bo;
     const int cnt = nbuf * kWave + bcount;
     if (cnt) flush(cnt);
   }
@@ -1370,7 +1424,8 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
 template <int KT, int TW>
 FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                               int32_t *pos, int2 *rxy, uint32_t *inq, uint32_t *touched,
-                              TeamLds *tl, int W, Queue Q, int64_t *cnt, int64_t *tk) {
+                              uint32_t *ord, TeamLds *tl, int W, Queue Q, int64_t *cnt,
+                              int64_t *tk) {
   constexpr int GS = KT <= 16 ? 16 : 32;  // lanes per evaluated city
   constexpr int G = kWave / GS;           // cities evaluated together
   const int n = I.n, lane = lane_id();
@@ -1464,7 +1519,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     cnt[CNT_SWEEPS]++;
     const int64_t t2 = ticks();
     const int pushed =
-        uniform_i(sweep<KT, TW>(I, flags, W, Q, route, pos, rxy, inq, touched, tl));
+        uniform_i(sweep<KT, TW>(I, flags, W, Q, route, pos, rxy, inq, touched, ord, tl));
     tk[3] += ticks() - t2;
     if (pushed == 0) break;
   }
@@ -1478,7 +1533,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
 // ===================================================================== //
 template <int KT, int TW>
 FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *vis,
-                          int32_t *route, int32_t *pos, int2 *rxy) {
+                          uint32_t *ord, int32_t *route, int32_t *pos, int2 *rxy) {
   Draws D;
   for (;;) {
     team_sync();
@@ -1505,7 +1560,9 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
       nearest_part<TW>(I, team_arg(tl, 0), w, vis, tl, md, mj);
     } else if (op == OP_SWEEP) {
       sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, route, pos,
-                         rxy, tl);
+                         rxy);
+    } else if (op == OP_ORDMARK) {
+      ord_mark_part<TW>(I, (I.n + 31) >> 5, w, vis, ord);
     }
     team_sync();
   }
@@ -1515,7 +1572,7 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
 // One ant: construction + local search.  mode 0: ant `ant` of iteration
 // st->iter + 1.  mode 1: initial solution (nearest neighbour + LS over all
 // cities) written to the global best.
-//   lds: [team area][visited W][listed W][queue ring I.lcap].
+//   lds: [team area][visited W][listed W][sweep order W][queue ring I.lcap].
 // ===================================================================== //
 template <int KT, int TW>
 FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
@@ -1524,6 +1581,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   TeamLds *tl = (TeamLds *)lds;
   uint32_t *vis = lds + team_words<TW>();
   uint32_t *inq = vis + W;
+  uint32_t *ord = inq + W;
   int32_t *route = I.routes + (size_t)ant * (size_t)n;
   int32_t *pos = I.pos + (size_t)ant * (size_t)n;
   int32_t *ring = I.ring + (size_t)ant * (size_t)n;
@@ -1531,7 +1589,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   if (TW > 1) {
     const int w = uniform_i((int)(threadIdx.x >> 6));
     if (w > 0) {
-      team_helper<KT, TW>(I, ant, w, tl, vis, route, pos, rxy);
+      team_helper<KT, TW>(I, ant, w, tl, vis, ord, route, pos, rxy);
       return;
     }
   }
@@ -1551,7 +1609,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   uint32_t flags = I.ls_flags;
   const int lcap = I.lcap;
   Queue Q;
-  Q.lr = (int32_t *)(inq + W);
+  Q.lr = (int32_t *)(ord + W);
   Q.gr = ring;
   if (init) {
     // the initial solution reports only its local-search counters
@@ -1560,7 +1618,8 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
     flags = LS_2OPT | LS_SWEEP | (I.ls_flags & LS_OROPT);
     Q.in_lds = n <= lcap ? 1 : 0;
     Q.cap = Q.in_lds ? lcap : n;
-    for (int i = lane; i < n; i += kWave) (Q.in_lds ? Q.lr : ring)[i] = i;
+    // every city listed, in ascending original number
+    for (int i = lane; i < n; i += kWave) (Q.in_lds ? Q.lr : ring)[i] = I.int_of[i];
     for (int w = lane; w < W; w += kWave) {
       const int rem = n - w * 32;
       const uint32_t full = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
@@ -1584,6 +1643,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   }
   Q.head = 0;
   Q.tail = Q.count == Q.cap ? 0 : Q.count;
+  for (int w = lane; w < W; w += kWave) ord[w] = 0u;  // sweeps leave it clear
   wave_fence();
   flags = (uint32_t)uniform_i((int)flags);
   Q.head = uniform_i(Q.head);
@@ -1592,7 +1652,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   Q.cap = uniform_i(Q.cap);
   Q.in_lds = uniform_i(Q.in_lds);
   if (flags & (LS_2OPT | LS_OROPT))
-    len -= local_search<KT, TW>(I, flags, route, pos, rxy, inq, vis, tl, W, Q, cnt, tk);
+    len -= local_search<KT, TW>(I, flags, route, pos, rxy, inq, vis, ord, tl, W, Q, cnt, tk);
   if (TW > 1) {
     if (lane == 0) tl->op = OP_EXIT;
     team_sync();
