@@ -97,8 +97,10 @@ FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, Tea
   const int lane = lane_id();
   const int2 xu = I.xy[u];
   const int W = (I.n + 31) >> 5;
+  // distances only; equal distances are settled by original number below
   int64_t bd = INT64_MAX;
-  int bo = 0x7fffffff, bj = 0x7fffffff;
+  int bj = 0x7fffffff;
+  bool tie = false;
   for (int wi = w * kWave + lane; wi < W; wi += TW * kWave) {
     uint32_t free_bits = ~vis[wi];
     const int rem = I.n - wi * 32;
@@ -107,17 +109,46 @@ FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, Tea
       const int j = wi * 32 + __builtin_ctz(free_bits);
       free_bits &= free_bits - 1;
       const int64_t d = (int64_t)sqd_u64(xu, I.xy[j]);
-      const int o = I.orig_of[j];
-      if (d < bd || (d == bd && o < bo)) {
+      if (d < bd) {
         bd = d;
-        bo = o;
         bj = j;
+        tie = false;
+      } else if (d == bd) {
+        tie = true;
       }
     }
   }
   md = wave_min_i64(bd);
-  const int mo = wave_min_i32(bd == md ? bo : 0x7fffffff);
-  mj = wave_min_i32(bd == md && bo == mo ? bj : 0x7fffffff);
+  int mo = 0x7fffffff;
+  mj = 0x7fffffff;
+  if (md != INT64_MAX) {
+    const uint64_t at = ballot(bd == md);
+    if (__builtin_popcountll(at) == 1 && !ballot(bd == md && tie)) {
+      mj = readlane_i(bj, ctz64(at));
+      mo = uniform_i(I.orig_of[mj]);
+    } else {
+      // several cities at distance md: the smallest original number
+      int bo = 0x7fffffff, bj2 = 0x7fffffff;
+      for (int wi = w * kWave + lane; wi < W; wi += TW * kWave) {
+        uint32_t free_bits = ~vis[wi];
+        const int rem = I.n - wi * 32;
+        if (rem < 32) free_bits &= (1u << rem) - 1u;
+        while (free_bits) {
+          const int j = wi * 32 + __builtin_ctz(free_bits);
+          free_bits &= free_bits - 1;
+          if ((int64_t)sqd_u64(xu, I.xy[j]) == md) {
+            const int o = I.orig_of[j];
+            if (o < bo) {
+              bo = o;
+              bj2 = j;
+            }
+          }
+        }
+      }
+      mo = wave_min_i32(bo);
+      mj = wave_min_i32(bo == mo ? bj2 : 0x7fffffff);
+    }
+  }
   if (TW > 1 && lane == 0) {
     tl->part[w] = md;
     tl->f[w] = mo;
