@@ -97,7 +97,7 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   b += 4 * align_up(4 * N * (uint64_t)k);   // cl, cost, eta, tau
   b += 4 * align_up(4 * NB * (uint64_t)k);  // source-ordered city, weight, position, cost
   b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
-  b += 4 * align_up(4 * N) + align_up(8 * N); // source route/pos/edge costs, adjacency, global best
+  b += 4 * align_up(4 * N) + 2 * align_up(8 * N); // source route/pos/edge costs/coordinates, adjacency, global best
   b += 2 * align_up(4 * N);                   // label maps
   b += 3 * align_up(4 * N * A) + align_up(8 * N * A);  // ant routes, pos, rings, tour coordinates
   b += align_up(8 * A) + 2 * align_up(8 * A * faco::NCNT) + align_up(128 * A);
@@ -326,6 +326,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   ALLOC(gb_route, int32_t, N);
   ALLOC(src_adj, int2, N);
   ALLOC(src_d, int32_t, N);
+  ALLOC(src_xy, int2, N);
   ALLOC(routes, int32_t, N * A);
   ALLOC(pos, int32_t, N * A);
   ALLOC(ring, int32_t, N * A);

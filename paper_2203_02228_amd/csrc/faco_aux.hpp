@@ -81,7 +81,9 @@ FACO_DEV void run_source(const Inst &I, int i, int init) {
   I.src_route[i] = node;
   I.src_pos[node] = i;
   I.src_adj[node] = make_int2(next, prev);
-  I.src_d[i] = cost(I.xy[node], I.xy[next]);
+  const int2 xn = I.xy[node];
+  I.src_xy[i] = xn;
+  I.src_d[i] = cost(xn, I.xy[next]);
 }
 
 __global__ void __launch_bounds__(256) source_kernel(Inst I, int init) {

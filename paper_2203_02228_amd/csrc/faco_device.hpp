@@ -59,6 +59,7 @@ struct Inst {
   int32_t *ssp;       // source position of the candidate
   int32_t *sd;        // cost of the candidate edge
   int32_t *src_d;     // [n] cost of the source edge from position i to i + 1
+  int2 *src_xy;       // [n] coordinates of the city at source position i
   int32_t *routes, *pos, *ring;
   int2 *rxy;          // [A][n] coordinates of routes[a][p] (tour order)
   int64_t *lens, *cnt, *cnt_acc;

@@ -239,11 +239,13 @@ FACO_DEV void copy_rounds(const Inst &I, int pcur, int dir, int k, int w, TeamLd
   int app = 0, last = -1;
   for (int r = 0;; ++r) {
     int cc[4], dd[4];
+    int2 cx[4];
     bool vc[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int q = wrap_off(pcur, dir * (w * RW + h * kWave + lane + 1), n);
       cc[h] = I.src_route[q];
+      cx[h] = I.src_xy[q];
       dd[h] = I.src_d[dir > 0 ? (q == 0 ? n - 1 : q - 1) : q];
     }
 #pragma unroll
@@ -269,7 +271,7 @@ FACO_DEV void copy_rounds(const Inst &I, int pcur, int dir, int k, int w, TeamLd
       if (idx < J) {
         route[k + idx] = cc[h];
         pos[cc[h]] = k + idx;
-        rxy[k + idx] = I.xy[cc[h]];
+        rxy[k + idx] = cx[h];
         bit_set(vis, cc[h]);
         dsum += dd[h];
       }
@@ -298,21 +300,23 @@ FACO_DEV int copy_from(const Inst &I, int pv, int &k, int &u, int &pu, int64_t &
   const int n = I.n, lane = lane_id();
   const int qf = wrap_off(pv, lane + 1, n), qb = wrap_off(pv, -lane - 1, n);
   const int cf = I.src_route[qf], cb = I.src_route[qb];
+  const int2 xf = I.src_xy[qf], xb = I.src_xy[qb];
   const int df = I.src_d[qf == 0 ? n - 1 : qf - 1], db = I.src_d[qb];
   const uint64_t mf = ballot(bit_get(vis, cf));
   const int jf = mf ? ctz64(mf) : kWave;
   int dir, j, c, d;
+  int2 cxy;
   if (jf > 0) {
-    dir = 1; j = jf; c = cf; d = df;
+    dir = 1; j = jf; c = cf; d = df; cxy = xf;
   } else {
     const uint64_t mb = ballot(bit_get(vis, cb));
-    dir = -1; j = mb ? ctz64(mb) : kWave; c = cb; d = db;
+    dir = -1; j = mb ? ctz64(mb) : kWave; c = cb; d = db; cxy = xb;
   }
   if (j == 0) return 0;
   if (lane < j) {
     route[k + lane] = c;
     pos[c] = k + lane;
-    rxy[k + lane] = I.xy[c];
+    rxy[k + lane] = cxy;
     bit_set(vis, c);
   }
   len += wave_sum_i64(lane < j ? (int64_t)d : 0);
@@ -386,6 +390,7 @@ FACO_DEV void window_part(const Inst &I, uint64_t t, uint64_t ant, uint64_t step
   const int rpos = wrap_off(pu, dir * g, n);      // position of q_g
   const int qpos = wrap_off(pu, dir * (g + 1), n);
   const int qn = I.src_route[qpos];                // q_{g+1}
+  const int2 qxy = I.src_xy[qpos];
   const int ed = I.src_d[dir > 0 ? rpos : qpos];   // cost q_g -> q_{g+1}
   const size_t row = srow(rpos, 0, K);
   int c[KT], sp[KT], cd[KT];
@@ -451,7 +456,7 @@ FACO_DEV void window_part(const Inst &I, uint64_t t, uint64_t ant, uint64_t step
   if (g < acc) {
     route[k + g] = qn;
     pos[qn] = k + g;
-    rxy[k + g] = I.xy[qn];
+    rxy[k + g] = qxy;
     bit_set(vis, qn);
   }
   const int64_t ssum = wave_sum_i64(g < acc ? (int64_t)ed : 0);
