@@ -53,7 +53,7 @@ FACO_DEV int wrap_off(int q, int off, int n) {
 constexpr int kMaxTeam = 8;
 enum TeamOp {
   OP_EXIT = 0, OP_REVERSE = 1, OP_SHIFT = 2, OP_WINDOW = 3, OP_SWEEP = 4, OP_COPY = 5,
-  OP_NEAREST = 6, OP_ORDMARK = 7
+  OP_NEAREST = 6
 };
 struct TeamLds {
   int op;
@@ -62,8 +62,7 @@ struct TeamLds {
   int f[2 * kMaxTeam];           // per-wave first stop (window, copy: by round parity)
   int res[4];                    // window: last followed city; decision v, dv, pv
   int64_t part[kMaxTeam];        // window: per-wave sums of source edge costs
-  uint64_t mask[kMaxTeam];       // sweep: per-wave ballots
-  int cities[kMaxTeam * kWave];  // sweep: cities to test, in order
+  int cities[kMaxTeam * kWave];  // sweep: the batch of cities to test
 };
 template <int TW>
 constexpr int team_words() {
@@ -1333,20 +1332,47 @@ FACO_DEV void push_all(int n, const int *c, Queue &Q, uint32_t *inq, uint32_t *t
   Q.count += np;
 }
 
-// Sweep: test every touched city in ascending original number and list the
-// improvable ones.  First the touched cities' original numbers are marked
-// in the `ord` bitmap (wave w of a team takes the w-th share of the words);
-// then `ord` is read in ascending order, cities are tested 64 TW at a time
-// (wave w takes the w-th 64, translating original numbers back), and the
-// improvable ones are listed in that order.
-template <int TW>
-FACO_DEV void ord_mark_part(const Inst &I, int W, int w, const uint32_t *touched,
-                            uint32_t *ord) {
+// Sweep: test every touched city and list the improvable ones in ascending
+// original number.  The touched cities are tested in label order, 64 TW at a
+// time (wave w takes the w-th 64): labels follow a space-filling curve, so the
+// cities of a batch have nearby candidate rows and tour neighbourhoods.  Each
+// improvable city's original number is marked in the `ord` bitmap; `ord` is
+// then read in ascending order and the marked cities are listed in that
+// order (and `ord` is left clear).  The tour does not change during a sweep,
+// so the order of the tests does not matter.
+template <int KT, int TW>
+FACO_DEV void sweep_part(const Inst &I, uint32_t flags, int count, int w, TeamLds *tl,
+                         uint32_t *ord, const int32_t *route, const int32_t *pos,
+                         const int2 *rxy) {
+  const int i = w * kWave + lane_id();
+  if (i < count) {
+    const int x = tl->cities[i];
+    const int ox = I.orig_of[x];
+    if (has_improving<KT>(I, flags, x, route, pos, rxy)) bit_set(ord, ox);
+  }
+}
+
+template <int KT, int TW>
+FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
+                   const int32_t *route, const int32_t *pos, const int2 *rxy,
+                   uint32_t *inq, uint32_t *touched, uint32_t *ord, TeamLds *tl) {
   const int lane = lane_id();
-  const int w_lo = (int)((int64_t)W * w / TW), w_hi = (int)((int64_t)W * (w + 1) / TW);
-  int bx = 0, bcount = 0;
-  for (int w0 = w_lo; w0 < w_hi; w0 += kWave) {
-    const uint32_t word = (w0 + lane < w_hi) ? touched[w0 + lane] : 0u;
+  int bx = -1, bcount = 0, nbuf = 0;
+  auto test = [&](int cnt) {
+    if (TW == 1) {
+      if (lane < cnt) {
+        const int ox = I.orig_of[bx];
+        if (has_improving<KT>(I, flags, bx, route, pos, rxy)) bit_set(ord, ox);
+      }
+      return;
+    }
+    // cnt cities sit in tl->cities[0..cnt)
+    team_post(tl, OP_SWEEP, cnt, (int)flags);
+    sweep_part<KT, TW>(I, flags, cnt, 0, tl, ord, route, pos, rxy);
+    team_sync();
+  };
+  for (int w0 = 0; w0 < W; w0 += kWave) {
+    const uint32_t word = (w0 + lane < W) ? touched[w0 + lane] : 0u;
     uint64_t nz = ballot(word != 0u);
     while (nz) {
       const int l = ctz64(nz);
@@ -1357,88 +1383,12 @@ FACO_DEV void ord_mark_part(const Inst &I, int W, int w, const uint32_t *touched
         bits &= bits - 1;
         if (lane == bcount) bx = (w0 + l) * 32 + bpos;
         if (++bcount == kWave) {
-          bit_set(ord, I.orig_of[bx]);
-          bcount = 0;
-        }
-      }
-    }
-  }
-  if (lane < bcount) bit_set(ord, I.orig_of[bx]);
-}
-
-template <int KT, int TW>
-FACO_DEV void sweep_part(const Inst &I, uint32_t flags, int count, int w, TeamLds *tl,
-                         const int32_t *route, const int32_t *pos, const int2 *rxy) {
-  const int i = w * kWave + lane_id();
-  bool f = false;
-  if (i < count) {
-    const int x = I.int_of[tl->cities[i]];
-    tl->cities[i] = x;
-    f = has_improving<KT>(I, flags, x, route, pos, rxy);
-  }
-  const uint64_t m = ballot(f);
-  if (lane_id() == 0) tl->mask[w] = m;
-}
-
-template <int KT, int TW>
-FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
-                   const int32_t *route, const int32_t *pos, const int2 *rxy,
-                   uint32_t *inq, uint32_t *touched, uint32_t *ord, TeamLds *tl) {
-  const int lane = lane_id();
-  int pushed = 0;
-  if (TW > 1) {
-    team_post(tl, OP_ORDMARK);
-    ord_mark_part<TW>(I, W, 0, touched, ord);
-    team_sync();
-  } else {
-    ord_mark_part<1>(I, W, 0, touched, ord);
-    wave_fence();
-  }
-  int bo = -1, bcount = 0, nbuf = 0;
-  auto flush = [&](int cnt) {
-    if (TW == 1) {
-      bool f = false;
-      int x = 0;
-      if (lane < cnt) {
-        x = I.int_of[bo];
-        f = has_improving<KT>(I, flags, x, route, pos, rxy);
-      }
-      pushed += __builtin_popcountll(ballot(f));
-      push_lanes(I.n, x, f, Q, inq, touched);
-      return;
-    }
-    // cnt original numbers sit in tl->cities[0..cnt); the team translates
-    // them in place and tests them
-    team_post(tl, OP_SWEEP, cnt, (int)flags);
-    sweep_part<KT, TW>(I, flags, cnt, 0, tl, route, pos, rxy);
-    team_sync();
-    for (int j = 0; j * kWave < cnt; ++j) {
-      const int c = tl->cities[j * kWave + lane];
-      const uint64_t m = uniform_u64(tl->mask[j]);
-      pushed += __builtin_popcountll(m);
-      push_lanes(I.n, c, ((m >> lane) & 1ull) != 0, Q, inq, touched);
-    }
-  };
-  for (int w0 = 0; w0 < W; w0 += kWave) {
-    const uint32_t word = (w0 + lane < W) ? ord[w0 + lane] : 0u;
-    if (w0 + lane < W) ord[w0 + lane] = 0u;  // left clear for the next sweep
-    uint64_t nz = ballot(word != 0u);
-    while (nz) {
-      const int l = ctz64(nz);
-      nz &= nz - 1;
-      uint32_t bits = (uint32_t)readlane_i((int)word, l);
-      while (bits) {
-        const int bpos = __builtin_ctz(bits);
-        bits &= bits - 1;
-        const int o = (w0 + l) * 32 + bpos;
-        if (lane == bcount) bo = o;
-        if (++bcount == kWave) {
           if (TW == 1) {
-            flush(kWave);
+            test(kWave);
           } else {
-            tl->cities[nbuf * kWave + lane] = bo;
+            tl->cities[nbuf * kWave + lane] = bx;
             if (++nbuf == TW) {
-              flush(TW * kWave);
+              test(TW * kWave);
               nbuf = 0;
             }
           }
@@ -1448,12 +1398,41 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
     }
   }
   if (TW == 1) {
-    if (bcount) flush(bcount);
+    if (bcount) test(bcount);
   } else {
-    if (bcount) tl->cities[nbuf * kWave + lane] = bo;
+    if (bcount) tl->cities[nbuf * kWave + lane] = bx;
     const int cnt = nbuf * kWave + bcount;
-    if (cnt) flush(cnt);
+    if (cnt) test(cnt);
   }
+  wave_fence();
+  // list the marked cities, ascending original number, 64 at a time
+  int pushed = 0, bo = -1;
+  bcount = 0;
+  auto list = [&](int cnt) {
+    const int x = lane < cnt ? I.int_of[bo] : 0;
+    pushed += cnt;
+    push_lanes(I.n, x, lane < cnt, Q, inq, touched);
+  };
+  for (int w0 = 0; w0 < W; w0 += kWave) {
+    const uint32_t word = (w0 + lane < W) ? ord[w0 + lane] : 0u;
+    if (w0 + lane < W) ord[w0 + lane] = 0u;
+    uint64_t nz = ballot(word != 0u);
+    while (nz) {
+      const int l = ctz64(nz);
+      nz &= nz - 1;
+      uint32_t bits = (uint32_t)readlane_i((int)word, l);
+      while (bits) {
+        const int bpos = __builtin_ctz(bits);
+        bits &= bits - 1;
+        if (lane == bcount) bo = (w0 + l) * 32 + bpos;
+        if (++bcount == kWave) {
+          list(kWave);
+          bcount = 0;
+        }
+      }
+    }
+  }
+  if (bcount) list(bcount);
   return pushed;
 }
 
@@ -1595,10 +1574,8 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
       int mj;
       nearest_part<TW>(I, team_arg(tl, 0), w, vis, tl, md, mj);
     } else if (op == OP_SWEEP) {
-      sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, route, pos,
-                         rxy);
-    } else if (op == OP_ORDMARK) {
-      ord_mark_part<TW>(I, (I.n + 31) >> 5, w, vis, ord);
+      sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, ord, route,
+                         pos, rxy);
     }
     team_sync();
   }
