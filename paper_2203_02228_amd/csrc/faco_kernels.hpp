@@ -973,20 +973,26 @@ FACO_DEV Move extract_move(const Inst &I, const GroupEval &R, int j) {
 }
 
 // Lane-serial test used by the sweep (one city per lane): does x have an
-// improving move?  Loads are issued before gains are formed; candidate lists
-// are sorted by distance, so a slot that fails the pruning test ends the scan.
+// improving move?  Candidate lists are sorted by distance and every move
+// through candidate b needs d(x, b) below the longer tour edge at x, so only
+// a prefix of the list matters.  The candidates are taken CK at a time (a
+// chunk is loaded, then tested), while a lane of the wave still needs them;
+// inside a chunk every array index is a compile-time constant, so nothing
+// is indexed at run time.
 template <int KT>
 FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
                             const int32_t *route, const int32_t *pos, const int2 *rxy) {
+  constexpr int CK = KT < 8 ? KT : 8;
   const int n = I.n, K = I.k;
   const size_t row = (size_t)x * (size_t)K;
-  const int px = pos[x];
-  int b[KT], dxb[KT];
+  // first chunk of the list with the city's own data
+  int cb[CK], cd[CK];
 #pragma unroll
-  for (int s = 0; s < KT; ++s) {
-    b[s] = s < K ? I.cl[row + s] : x;
-    dxb[s] = s < K ? I.cl_d[row + s] : 0;
+  for (int j = 0; j < CK; ++j) {
+    cb[j] = j < K ? I.cl[row + j] : x;
+    cd[j] = j < K ? I.cl_d[row + j] : 0x7fffffff;
   }
+  const int px = pos[x];
   const int2 cx = I.xy[x];
   int xnx[7], xny[7];
 #pragma unroll
@@ -994,73 +1000,89 @@ FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
     const int2 q = rxy[wrapn(px + j - 3, n)];
     xnx[j] = q.x; xny[j] = q.y;
   }
-  int pb[KT], xbx[KT], xby[KT];
-#pragma unroll
-  for (int s = 0; s < KT; ++s) {
-    pb[s] = pos[b[s]];
-    const int2 q = I.xy[b[s]];
-    xbx[s] = q.x; xby[s] = q.y;
-  }
-  int xbsx[KT], xbsy[KT], xbpx[KT], xbpy[KT];
-#pragma unroll
-  for (int s = 0; s < KT; ++s) {
-    const int2 q1 = rxy[pb[s] + 1 == n ? 0 : pb[s] + 1];
-    const int2 q2 = rxy[pb[s] == 0 ? n - 1 : pb[s] - 1];
-    xbsx[s] = q1.x; xbsy[s] = q1.y;
-    xbpx[s] = q2.x; xbpy[s] = q2.y;
-  }
 #define XN(j) make_int2(xnx[j], xny[j])
-#define XB(s) make_int2(xbx[s], xby[s])
-#define XBS(s) make_int2(xbsx[s], xbsy[s])
-#define XBP(s) make_int2(xbpx[s], xbpy[s])
-  if (flags & LS_2OPT) {
-    const int d_s = cost(cx, XN(4)), d_p = cost(XN(2), cx);
+  const bool two = (flags & LS_2OPT) != 0, orr = (flags & LS_OROPT) != 0;
+  const int d_s = cost(cx, XN(4)), d_p = cost(XN(2), cx);
+  // Or-opt, per segment slot: where the segment starts, its length, the
+  // endpoint that meets the insertion edge, the removed edge at x (0 when
+  // the slot cannot apply: no candidate cost is below it) and the removal
+  // gain
+  int sf[kOrSlots], sl[kOrSlots], srem[kOrSlots], sg[kOrSlots], sox[kOrSlots], soy[kOrSlots];
+  int lim = two ? (d_s > d_p ? d_s : d_p) : 0;
+  const int Lmax = or_lmax(I);
 #pragma unroll
-    for (int s = 0; s < KT; ++s) {
-      if (s >= K) break;
-      const int d_xb = dxb[s];
-      if (d_s <= d_xb && d_p <= d_xb) break;
-      if (d_s > d_xb && d_s + cost(XB(s), XBS(s)) - d_xb - cost(XN(4), XBS(s)) > 0) return true;
-      if (d_p > d_xb && d_p + cost(XBP(s), XB(s)) - d_xb - cost(XN(2), XBP(s)) > 0) return true;
-    }
+  for (int vi = 0; vi < kOrSlots; ++vi) {
+    int dir, L, lf, ll, lp, lq;
+    or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
+    sl[vi] = L;
+    sf[vi] = dir == 0 ? px : wrapn(px - L + 1, n);
+    const int2 xo = dir == 0 ? XN(ll) : XN(lf);
+    sox[vi] = xo.x;
+    soy[vi] = xo.y;
+    const int rem = dir == 0 ? d_p : d_s;
+    srem[vi] = (orr && L <= Lmax && cd[0] < rem) ? rem : 0;
+    sg[vi] = cost(XN(lp), XN(lf)) + cost(XN(ll), XN(lq)) - cost(XN(lp), XN(lq));
+    lim = srem[vi] > lim ? srem[vi] : lim;
   }
-  if (flags & LS_OROPT) {
-    const int Lmax = or_lmax(I);
+  bool found = false;
+  for (int c0 = 0;;) {
+    int pb[CK], xbx[CK], xby[CK];
 #pragma unroll
-    for (int vi = 0; vi < kOrSlots; ++vi) {
-      int dir, L, lf, ll, lp, lq;
-      or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
-      if (L > Lmax) continue;
-      const int fpos = dir == 0 ? px : wrapn(px - L + 1, n);
-      const int2 xo = dir == 0 ? XN(ll) : XN(lf);
-      const int rem = dir == 0 ? cost(XN(lp), cx) : cost(cx, XN(lq));
-      if (!(dxb[0] < rem)) continue;
-      const int g_rem = cost(XN(lp), XN(lf)) + cost(XN(ll), XN(lq)) - cost(XN(lp), XN(lq));
+    for (int j = 0; j < CK; ++j) {
+      pb[j] = pos[cb[j]];
+      const int2 q = I.xy[cb[j]];
+      xbx[j] = q.x; xby[j] = q.y;
+    }
+    int sx[CK], sy[CK], qx[CK], qy[CK];  // succ and pred of b
 #pragma unroll
-      for (int s = 0; s < KT; ++s) {
-        if (s >= K) break;
-        const int d_xb = dxb[s];
-        if (!(d_xb < rem)) break;
-        if (wrapn(pb[s] - fpos, n) < L) continue;
-        const int pbs = pb[s] + 1 == n ? 0 : pb[s] + 1, pbp = pb[s] == 0 ? n - 1 : pb[s] - 1;
-        // costs are >= 0: no cost of the new edge is needed unless the rest
-        // of the gain is positive
-        if (wrapn(pbs - fpos, n) >= L) {
-          const int rest = g_rem + cost(XB(s), XBS(s)) - d_xb;
-          if (rest > 0 && rest - cost(xo, XBS(s)) > 0) return true;
-        }
-        if (wrapn(pbp - fpos, n) >= L) {
-          const int rest = g_rem + cost(XB(s), XBP(s)) - d_xb;
-          if (rest > 0 && rest - cost(xo, XBP(s)) > 0) return true;
+    for (int j = 0; j < CK; ++j) {
+      const int2 q1 = rxy[pb[j] + 1 == n ? 0 : pb[j] + 1];
+      const int2 q2 = rxy[pb[j] == 0 ? n - 1 : pb[j] - 1];
+      sx[j] = q1.x; sy[j] = q1.y;
+      qx[j] = q2.x; qy[j] = q2.y;
+    }
+#pragma unroll
+    for (int j = 0; j < CK; ++j) {
+      const int d_xb = cd[j];
+      if (!found && c0 + j < K && d_xb < lim) {
+        const int2 xb = make_int2(xbx[j], xby[j]);
+        const int2 xbs = make_int2(sx[j], sy[j]), xbp = make_int2(qx[j], qy[j]);
+        const int es = cost(xb, xbs) - d_xb, ep = cost(xbp, xb) - d_xb;
+        if (two && d_s > d_xb && d_s + es - cost(XN(4), xbs) > 0) found = true;
+        if (two && d_p > d_xb && d_p + ep - cost(XN(2), xbp) > 0) found = true;
+        const int pbs = pb[j] + 1 == n ? 0 : pb[j] + 1, pbp = pb[j] == 0 ? n - 1 : pb[j] - 1;
+#pragma unroll
+        for (int vi = 0; vi < kOrSlots; ++vi) {
+          const int L = sl[vi], fpos = sf[vi];
+          if (!found && d_xb < srem[vi] && wrapn(pb[j] - fpos, n) >= L) {
+            const int2 xo = make_int2(sox[vi], soy[vi]);
+            // costs are >= 0: no cost of the new edge is needed unless the
+            // rest of the gain is positive
+            if (wrapn(pbs - fpos, n) >= L) {
+              const int rest = sg[vi] + es;
+              if (rest > 0 && rest - cost(xo, xbs) > 0) found = true;
+            }
+            if (wrapn(pbp - fpos, n) >= L) {
+              const int rest = sg[vi] + ep;
+              if (rest > 0 && rest - cost(xo, xbp) > 0) found = true;
+            }
+          }
         }
       }
     }
+    c0 += CK;
+    if (c0 >= K) break;
+    // the next chunk, if a lane of the wave still needs it
+    const int dn = I.cl_d[row + c0];
+    if (!ballot(!found && dn < lim)) break;
+#pragma unroll
+    for (int j = 0; j < CK; ++j) {
+      cb[j] = c0 + j < K ? I.cl[row + c0 + j] : x;
+      cd[j] = c0 + j < K ? I.cl_d[row + c0 + j] : 0x7fffffff;
+    }
   }
 #undef XN
-#undef XB
-#undef XBS
-#undef XBP
-  return false;
+  return found;
 }
 
 constexpr int kChunks = 16;  // 64-element chunks in flight per wave and round
