@@ -96,24 +96,50 @@ FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, Tea
   const int lane = lane_id();
   const int2 xu = I.xy[u];
   const int W = (I.n + 31) >> 5;
-  // distances only; equal distances are settled by original number below
+  // distances only; equal distances are settled by original number below.
+  // Each lane takes the unvisited cities of its words kNearBatch at a time,
+  // so that their coordinate loads are in flight together.
+  constexpr int kNearBatch = 8;
   int64_t bd = INT64_MAX;
   int bj = 0x7fffffff;
   bool tie = false;
-  for (int wi = w * kWave + lane; wi < W; wi += TW * kWave) {
-    uint32_t free_bits = ~vis[wi];
+  auto free_word = [&](int wi) -> uint32_t {
+    if (wi >= W) return 0u;
+    uint32_t f = ~vis[wi];
     const int rem = I.n - wi * 32;
-    if (rem < 32) free_bits &= (1u << rem) - 1u;
-    while (free_bits) {
-      const int j = wi * 32 + __builtin_ctz(free_bits);
-      free_bits &= free_bits - 1;
-      const int64_t d = (int64_t)sqd_u64(xu, I.xy[j]);
-      if (d < bd) {
-        bd = d;
-        bj = j;
-        tie = false;
-      } else if (d == bd) {
-        tie = true;
+    if (rem < 32) f &= (1u << rem) - 1u;
+    return f;
+  };
+  int wi = w * kWave + lane;
+  uint32_t fb = free_word(wi);
+  for (;;) {
+    int jb[kNearBatch];
+    bool vb[kNearBatch];
+#pragma unroll
+    for (int k = 0; k < kNearBatch; ++k) {
+      while (fb == 0u && wi < W) {
+        wi += TW * kWave;
+        fb = free_word(wi);
+      }
+      vb[k] = fb != 0u;
+      jb[k] = vb[k] ? wi * 32 + __builtin_ctz(fb) : u;
+      fb &= fb - 1u;
+    }
+    if (!vb[0]) break;
+    int2 xb[kNearBatch];
+#pragma unroll
+    for (int k = 0; k < kNearBatch; ++k) xb[k] = I.xy[jb[k]];
+#pragma unroll
+    for (int k = 0; k < kNearBatch; ++k) {
+      if (vb[k]) {
+        const int64_t d = (int64_t)sqd_u64(xu, xb[k]);
+        if (d < bd) {
+          bd = d;
+          bj = jb[k];
+          tie = false;
+        } else if (d == bd) {
+          tie = true;
+        }
       }
     }
   }
