@@ -180,6 +180,19 @@ constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
 
 enum : uint64_t { kPurposeRoulette = 0, kPurposeStart = 1, kPurposeSource = 2 };
 
+// Full 128-bit product m * x from four 32 x 32 -> 64 partial products, each
+// with the carry-in folded into its addend (no partial sum overflows 64 bits:
+// (2^32 - 1)^2 + 2 (2^32 - 1) = 2^64 - 1), so each is one multiply-add.
+FACO_DEV void mulhilo64(uint64_t m, uint64_t x, uint64_t &hi, uint64_t &lo) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint32_t m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+  const uint64_t p00 = (uint64_t)x0 * m0;
+  const uint64_t t = (uint64_t)x1 * m0 + (p00 >> 32);
+  const uint64_t u = (uint64_t)x0 * m1 + (uint32_t)t;
+  hi = (uint64_t)x1 * m1 + ((t >> 32) + (u >> 32));
+  lo = (u << 32) | (uint32_t)p00;
+}
+
 FACO_DEV uint64_t philox_word0(uint64_t key0, uint64_t c0, uint64_t c1,
                                uint64_t c2, uint64_t c3) {
   uint64_t k0 = key0, k1 = 0;
@@ -189,8 +202,9 @@ FACO_DEV uint64_t philox_word0(uint64_t key0, uint64_t c0, uint64_t c1,
       k0 += kW0;
       k1 += kW1;
     }
-    uint64_t hi0 = __umul64hi(kM0, c0), lo0 = kM0 * c0;
-    uint64_t hi1 = __umul64hi(kM1, c2), lo1 = kM1 * c2;
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(kM0, c0, hi0, lo0);
+    mulhilo64(kM1, c2, hi1, lo1);
     uint64_t n0 = hi1 ^ c1 ^ k0;
     uint64_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
