@@ -93,6 +93,7 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   const uint64_t N = (uint64_t)n, A = (uint64_t)p->n_ants;
   uint64_t b = 0;
   b += align_up(8 * N);                    // xy
+  b += align_up(16 * ((N + 31) / 32));     // bounding boxes of 32-label words
   const uint64_t NB = (N + 63) / 64 * 64;   // source-ordered tables: whole 64-position blocks
   b += 4 * align_up(4 * N * (uint64_t)k);   // cl, cost, eta, tau
   b += 4 * align_up(4 * NB * (uint64_t)k);  // source-ordered city, weight, position, cost
@@ -310,6 +311,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   }                                                    \
   I.field = (type *)ptr;
   ALLOC(xy, int2, N);
+  ALLOC(wbox, int4, (N + 31) / 32);
   ALLOC(orig_of, int32_t, N);
   ALLOC(int_of, int32_t, N);
   ALLOC(cl, int32_t, N * K);
@@ -361,6 +363,24 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   }
   BTRY(hipMemcpyAsync((void *)I.xy, xy_int.data(), sizeof(int2) * N, hipMemcpyHostToDevice,
                       h->stream));
+  // bounding box of each bitmap word's 32 labels (the nearest-unvisited scan
+  // skips words whose box lies beyond its bound)
+  std::vector<int32_t> wbox(4 * ((N + 31) / 32));
+  for (size_t wi = 0; wi < (N + 31) / 32; ++wi) {
+    int32_t x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
+    for (size_t i = 32 * wi; i < std::min(N, 32 * wi + 32); ++i) {
+      x0 = std::min(x0, xy_int[2 * i]);
+      y0 = std::min(y0, xy_int[2 * i + 1]);
+      x1 = std::max(x1, xy_int[2 * i]);
+      y1 = std::max(y1, xy_int[2 * i + 1]);
+    }
+    wbox[4 * wi] = x0;
+    wbox[4 * wi + 1] = y0;
+    wbox[4 * wi + 2] = x1;
+    wbox[4 * wi + 3] = y1;
+  }
+  BTRY(hipMemcpyAsync((void *)I.wbox, wbox.data(), sizeof(int32_t) * wbox.size(),
+                      hipMemcpyHostToDevice, h->stream));
   BTRY(hipMemcpyAsync((void *)I.orig_of, h->orig_of.data(), sizeof(int32_t) * N,
                       hipMemcpyHostToDevice, h->stream));
   BTRY(hipMemcpyAsync((void *)I.int_of, h->int_of.data(), sizeof(int32_t) * N,

@@ -44,6 +44,7 @@ struct Inst {
   const int32_t *orig_of;
   const int32_t *int_of;
   const int2 *xy;     // [n] coordinates by internal label
+  const int4 *wbox;   // [(n + 31) / 32] bounding box (min x, min y, max x, max y) of labels 32 i ..
   const int32_t *cl;
   const int32_t *bll;
   const float *eta;

@@ -62,6 +62,7 @@ struct TeamLds {
   int f[2 * kMaxTeam];           // per-wave first stop (window, copy: by round parity)
   int res[4];                    // window: last followed city; decision v, dv, pv
   int64_t part[kMaxTeam];        // window: per-wave sums of source edge costs
+  int64_t ub[kMaxTeam];          // nearest: per-wave bounds
   int cities[kMaxTeam * kWave];  // sweep: the batch of cities to test
 };
 template <int TW>
@@ -87,22 +88,16 @@ FACO_DEV int team_arg(const TeamLds *tl, int i) { return uniform_i(tl->arg[i]); 
 // Backup list, then the nearest unvisited city (when no candidate of u is
 // unvisited).  Uniform result.
 // ===================================================================== //
-// Nearest unvisited city to u by (squared distance, id): lane l of wave w
-// scans bitmap words w * 64 + l, + 64 TW, ...; fully visited words are
-// skipped.  Each wave leaves its (distance, city) minimum in LDS (TW > 1).
+// Nearest unvisited city to u by (squared distance, original number): lane l
+// of wave w scans bitmap words w * 64 + l, + 64 TW, ...; fully visited words
+// and words whose bounding box lies beyond a bound are skipped.  Each wave
+// leaves its (distance, city) minimum in LDS (TW > 1).
 template <int TW>
 FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, TeamLds *tl,
                            int64_t &md, int &mj) {
   const int lane = lane_id();
   const int2 xu = I.xy[u];
   const int W = (I.n + 31) >> 5;
-  // distances only; equal distances are settled by original number below.
-  // Each lane takes the unvisited cities of its words kNearBatch at a time,
-  // so that their coordinate loads are in flight together.
-  constexpr int kNearBatch = 8;
-  int64_t bd = INT64_MAX;
-  int bj = 0x7fffffff;
-  bool tie = false;
   auto free_word = [&](int wi) -> uint32_t {
     if (wi >= W) return 0u;
     uint32_t f = ~vis[wi];
@@ -110,35 +105,90 @@ FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, Tea
     if (rem < 32) f &= (1u << rem) - 1u;
     return f;
   };
-  int wi = w * kWave + lane;
-  uint32_t fb = free_word(wi);
-  for (;;) {
-    int jb[kNearBatch];
-    bool vb[kNearBatch];
+  // A bound first: the nearest of the first unvisited cities of the TW 64
+  // bitmap words around u's (labels follow a space-filling curve, so these
+  // are close).  A word whose cities' bounding box lies farther than the
+  // bound cannot hold the nearest city (nor one tied with it) and is skipped.
+  int64_t ub = INT64_MAX;
+  {
+    constexpr int span = TW * kWave;
+    int lo = (u >> 5) - span / 2;
+    lo = lo > W - span ? W - span : lo;
+    lo = lo < 0 ? 0 : lo;
+    const int wi = lo + w * kWave + lane;
+    const uint32_t f = free_word(wi);
+    if (f) ub = (int64_t)sqd_u64(xu, I.xy[wi * 32 + __builtin_ctz(f)]);
+  }
+  ub = wave_min_i64(ub);
+  if (TW > 1) {
+    if (lane == 0) tl->ub[w] = ub;
+    team_sync();
+    ub = wave_min_i64(lane < TW ? tl->ub[lane] : INT64_MAX);
+  }
+  // distances only; equal distances are settled by original number below.
+  // Lane l of wave w takes words w 64 + l + i TW 64, i = 0, 1, ..., 32 at a
+  // time: their boxes are tested with the loads in flight together, then the
+  // unvisited cities of the kept words are taken kNearBatch at a time, so that
+  // their coordinate loads are in flight together too.
+  constexpr int kNearBatch = 8;
+  constexpr int stride = TW * kWave;
+  int64_t bd = INT64_MAX;
+  int bj = 0x7fffffff;
+  bool tie = false;
+  for (int g0 = w * kWave + lane; g0 < W; g0 += 32 * stride) {
+    uint32_t keep = 0u;
+    for (int k0 = 0; k0 < 32; k0 += 8) {
+      int4 bx[8];
+      bool has[8];
 #pragma unroll
-    for (int k = 0; k < kNearBatch; ++k) {
-      while (fb == 0u && wi < W) {
-        wi += TW * kWave;
-        fb = free_word(wi);
+      for (int k = 0; k < 8; ++k) {
+        const int wk = g0 + (k0 + k) * stride;
+        has[k] = free_word(wk) != 0u;
+        bx[k] = has[k] ? I.wbox[wk] : make_int4(0, 0, 0, 0);
       }
-      vb[k] = fb != 0u;
-      jb[k] = vb[k] ? wi * 32 + __builtin_ctz(fb) : u;
-      fb &= fb - 1u;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (has[k]) {
+          const int64_t dx = xu.x < bx[k].x ? (int64_t)bx[k].x - xu.x
+                                            : (xu.x > bx[k].z ? (int64_t)xu.x - bx[k].z : 0);
+          const int64_t dy = xu.y < bx[k].y ? (int64_t)bx[k].y - xu.y
+                                            : (xu.y > bx[k].w ? (int64_t)xu.y - bx[k].w : 0);
+          if (dx * dx + dy * dy <= ub) keep |= 1u << (k0 + k);
+        }
+      }
+      if (g0 + (k0 + 8) * stride >= W) break;
     }
-    if (!vb[0]) break;
-    int2 xb[kNearBatch];
+    int wi = 0;
+    uint32_t fb = 0u;
+    for (;;) {
+      int jb[kNearBatch];
+      bool vb[kNearBatch];
 #pragma unroll
-    for (int k = 0; k < kNearBatch; ++k) xb[k] = I.xy[jb[k]];
+      for (int k = 0; k < kNearBatch; ++k) {
+        while (fb == 0u && keep != 0u) {
+          wi = g0 + __builtin_ctz(keep) * stride;
+          keep &= keep - 1u;
+          fb = free_word(wi);
+        }
+        vb[k] = fb != 0u;
+        jb[k] = vb[k] ? wi * 32 + __builtin_ctz(fb) : u;
+        fb &= fb - 1u;
+      }
+      if (!vb[0]) break;
+      int2 xb[kNearBatch];
 #pragma unroll
-    for (int k = 0; k < kNearBatch; ++k) {
-      if (vb[k]) {
-        const int64_t d = (int64_t)sqd_u64(xu, xb[k]);
-        if (d < bd) {
-          bd = d;
-          bj = jb[k];
-          tie = false;
-        } else if (d == bd) {
-          tie = true;
+      for (int k = 0; k < kNearBatch; ++k) xb[k] = I.xy[jb[k]];
+#pragma unroll
+      for (int k = 0; k < kNearBatch; ++k) {
+        if (vb[k]) {
+          const int64_t d = (int64_t)sqd_u64(xu, xb[k]);
+          if (d < bd) {
+            bd = d;
+            bj = jb[k];
+            tie = false;
+          } else if (d == bd) {
+            tie = true;
+          }
         }
       }
     }
