@@ -1455,7 +1455,7 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
                    const int32_t *route, const int32_t *pos, const int2 *rxy,
                    uint32_t *inq, uint32_t *touched, uint32_t *ord, TeamLds *tl) {
   const int lane = lane_id();
-  int bx = -1, bcount = 0, nbuf = 0;
+  int bx = -1, bcount = 0;
   auto test = [&](int cnt) {
     if (TW == 1) {
       if (lane < cnt) {
@@ -1469,38 +1469,52 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
     sweep_part<KT, TW>(I, flags, cnt, 0, tl, ord, route, pos, rxy);
     team_sync();
   };
-  for (int w0 = 0; w0 < W; w0 += kWave) {
-    const uint32_t word = (w0 + lane < W) ? touched[w0 + lane] : 0u;
-    uint64_t nz = ballot(word != 0u);
-    while (nz) {
-      const int l = ctz64(nz);
-      nz &= nz - 1;
-      uint32_t bits = (uint32_t)readlane_i((int)word, l);
-      while (bits) {
-        const int bpos = __builtin_ctz(bits);
-        bits &= bits - 1;
-        if (lane == bcount) bx = (w0 + l) * 32 + bpos;
-        if (++bcount == kWave) {
-          if (TW == 1) {
+  if (TW == 1) {
+    for (int w0 = 0; w0 < W; w0 += kWave) {
+      const uint32_t word = (w0 + lane < W) ? touched[w0 + lane] : 0u;
+      uint64_t nz = ballot(word != 0u);
+      while (nz) {
+        const int l = ctz64(nz);
+        nz &= nz - 1;
+        uint32_t bits = (uint32_t)readlane_i((int)word, l);
+        while (bits) {
+          const int bpos = __builtin_ctz(bits);
+          bits &= bits - 1;
+          if (lane == bcount) bx = (w0 + l) * 32 + bpos;
+          if (++bcount == kWave) {
             test(kWave);
-          } else {
-            tl->cities[nbuf * kWave + lane] = bx;
-            if (++nbuf == TW) {
-              test(TW * kWave);
-              nbuf = 0;
-            }
+            bcount = 0;
           }
-          bcount = 0;
         }
       }
     }
-  }
-  if (TW == 1) {
     if (bcount) test(bcount);
   } else {
-    if (bcount) tl->cities[nbuf * kWave + lane] = bx;
-    const int cnt = nbuf * kWave + bcount;
-    if (cnt) test(cnt);
+    // every lane with touched bits in its word places its lowest one per
+    // pass (the order of the tests does not matter), slots by rank
+    constexpr int cap = TW * kWave;
+    int fill = 0;
+    for (int w0 = 0; w0 < W; w0 += kWave) {
+      uint32_t word = (w0 + lane < W) ? touched[w0 + lane] : 0u;
+      for (;;) {
+        const uint64_t m = ballot(word != 0u);
+        if (!m) break;
+        const int room = cap - fill;
+        const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (word != 0u && r < room) {
+          tl->cities[fill + r] = (w0 + lane) * 32 + __builtin_ctz(word);
+          word &= word - 1u;
+        }
+        const int np = __builtin_popcountll(m);
+        fill += np < room ? np : room;
+        if (fill == cap) {
+          test(cap);
+          fill = 0;
+        }
+      }
+    }
+    if (fill) test(fill);
   }
   wave_fence();
   // list the marked cities, ascending original number, 64 at a time
