@@ -56,13 +56,15 @@ def algorithmic_bytes_per_ant(cnt, n, k, bl):
     ACO step: candidate, pheromone and heuristic rows (12k) + source
     position/neighbours (12) + coordinates (8) + route/pos writes (8);
     copied city: source read (4) + coordinates (8) + route/pos writes (8);
-    backup pick: backup row (4 bl); fallback: coordinate scan (8n);
+    backup pick: backup row (4 bl); fallback: the bounding boxes of the
+    32-city bitmap words (n / 2; the coordinates of the few words within the
+    bound are not counted, so this term is a lower bound);
     LS pop: candidate row (4k) + per candidate, for both 2-opt loops,
     position, neighbour and two coordinates (2 * 24 k) + own neighbourhood (64);
     moved element: route read + route write + pos write (12)."""
     S, C, B, Fb = cnt[:, 0], cnt[:, 1], cnt[:, 2], cnt[:, 3]
     P, R = cnt[:, 5], cnt[:, 8]
-    return (S * (12 * k + 28) + 20 * C + B * 4 * bl + Fb * 8 * n +
+    return (S * (12 * k + 28) + 20 * C + B * 4 * bl + Fb * (n // 2) +
             P * (52 * k + 64) + 12 * R).astype(np.float64)
 
 
