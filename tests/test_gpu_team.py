@@ -88,3 +88,24 @@ def test_queue_capacity_errors():
             F.faco_set_queue_lds_capacity(bad)
         assert e.value.code == F.FACO_EINVAL
     F.faco_set_queue_lds_capacity(0)
+
+
+def test_team_nearest_on_grid(team):
+    """A 64 x 64 integer grid with one backup city: the nearest-unvisited scan
+    runs often, its bound and box pruning meet massive distance ties (settled
+    by original number), and the results must match the oracle's."""
+    import numpy as np
+    g1 = np.arange(64, dtype=np.int32) * 3 + 7
+    xy = np.stack(np.meshgrid(g1, g1, indexing="ij"), -1).reshape(-1, 2).astype(np.int32)
+    xy = xy[np.random.default_rng(5).permutation(len(xy))].copy()
+    say(f"[gpu] team={team} grid 64x64 nearest")
+    o, g = _pair(xy, threads=8, n_ants=5, min_new_edges=20, cl_size=4, bl_size=1)
+    _cmp_setup(o, g)
+    fallbacks = 0
+    for it in range(1, 4):
+        o.run(1)
+        F.faco_run_iterations(g, 1)
+        _cmp_iter(o, g, it)
+        fallbacks += int(F.faco_debug_get(g, F.FACO_DBG_COUNTERS)[:, 3].sum())
+    assert fallbacks > 0
+    g.close()
