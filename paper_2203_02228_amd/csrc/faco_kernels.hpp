@@ -14,6 +14,28 @@ namespace faco {
 // q mod n; the common cases (q within one period of [0, n)) avoid a division
 FACO_DEV int64_t ticks() { return (int64_t)wall_clock64(); }
 
+// Per-ant event counters and tick sums, one per lane (lane c holds entry c)
+// instead of one scalar register pair each: the local search needs the
+// scalar registers for its own state.  Updates take the first active lane's
+// increment, which is the wave's (every update sits in uniform control flow).
+struct LaneCounters {
+  int64_t v = 0;
+  struct Ref {
+    int64_t &v;
+    int c;
+    FACO_DEV void operator+=(int64_t d) {
+      d = (int64_t)uniform_u64((uint64_t)d);
+      v += lane_id() == c ? d : 0;
+    }
+    FACO_DEV void operator++(int) { v += lane_id() == c ? 1 : 0; }
+    FACO_DEV void operator=(int64_t x) {
+      x = (int64_t)uniform_u64((uint64_t)x);
+      v = lane_id() == c ? x : v;
+    }
+  };
+  FACO_DEV Ref operator[](int c) { return Ref{v, c}; }
+};
+
 FACO_DEV int wrapn(int q, int n) {
   if (q >= n) {
     q -= n;
@@ -233,7 +255,7 @@ FACO_DEV void nearest_part(const Inst &I, int u, int w, const uint32_t *vis, Tea
 
 template <int TW>
 FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, TeamLds *tl,
-                             int64_t *cnt) {
+                             LaneCounters &cnt) {
   const int lane = lane_id();
   int b = 0;
   bool bu = false;
@@ -269,7 +291,7 @@ FACO_DEV int select_fallback(const Inst &I, int u, const uint32_t *vis, TeamLds 
 // (lists are sorted by distance), else the fallback chain.  dv = its cost.
 template <int TW>
 FACO_DEV int select_greedy(const Inst &I, int u, const uint32_t *vis, TeamLds *tl, int &dv,
-                           int64_t *cnt) {
+                           LaneCounters &cnt) {
   const int K = I.k, lane = lane_id();
   const size_t row = (size_t)u * (size_t)K;
   const bool act = lane < K;
@@ -692,7 +714,7 @@ template <int KT, int TW>
 FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
                            int32_t *route, int32_t *pos, int2 *rxy, int32_t *ring,
                            uint32_t *vis, uint32_t *inq, TeamLds *tl, int W, int &nchk,
-                           int64_t *cnt, int64_t *tk) {
+                           LaneCounters &cnt, LaneCounters &tk) {
   const int n = I.n, lane = lane_id();
   for (int w = lane; w < W; w += kWave) {
     vis[w] = 0u;
@@ -1551,8 +1573,8 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
 template <int KT, int TW>
 FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                               int32_t *pos, int2 *rxy, uint32_t *inq, uint32_t *touched,
-                              uint32_t *ord, TeamLds *tl, int W, Queue Q, int64_t *cnt,
-                              int64_t *tk) {
+                              uint32_t *ord, TeamLds *tl, int W, Queue Q, LaneCounters &cnt,
+                              LaneCounters &tk) {
   constexpr int GS = KT <= 16 ? 16 : 32;  // lanes per evaluated city
   constexpr int G = kWave / GS;           // cities evaluated together
   const int n = I.n, lane = lane_id();
@@ -1611,9 +1633,9 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
           if (lane == 0) bit_clear(inq, e[g]);
           Q.head = Q.head + 1 == Q.cap ? 0 : Q.head + 1;
           Q.count--;
-          cnt[CNT_LS_POPS]++;
         }
       }
+      cnt[CNT_LS_POPS] += npop;
       if (j >= gcount) continue;
       const Move mv = extract_move<GS>(I, R, j);
       if (uniform_i(mv.kind) == 1) {
@@ -1718,12 +1740,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
       return;
     }
   }
-  int64_t cnt[NCNT];
-#pragma unroll
-  for (int c = 0; c < NCNT; ++c) cnt[c] = 0;
-  int64_t tk[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) tk[c] = 0;
+  LaneCounters cnt, tk;
   const bool init = mode == 1;
   const uint64_t t = (uint64_t)I.st->iter + 1;
   int nchk = 0;
@@ -1787,20 +1804,16 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
     if (lane == 0) {
       I.st->gb_len = len;
       I.st->init_len = len;
-#pragma unroll
-      for (int c = 0; c < NCNT; ++c) I.st->init_cnt[c] = cnt[c];
     }
-  } else if (lane == 0) {
-    I.lens[ant] = len;
-#pragma unroll
-    for (int c = 0; c < NCNT; ++c) {
-      I.cnt[(size_t)ant * NCNT + c] = cnt[c];
-      I.cnt_acc[(size_t)ant * NCNT + c] += cnt[c];
+    if (lane < NCNT) I.st->init_cnt[lane] = cnt.v;
+  } else {
+    if (lane == 0) I.lens[ant] = len;
+    if (lane < NCNT) {
+      I.cnt[(size_t)ant * NCNT + lane] = cnt.v;
+      I.cnt_acc[(size_t)ant * NCNT + lane] += cnt.v;
     }
-    int64_t *tr = I.ticks + (size_t)ant * 16;
     tk[4] = ticks() - t0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) tr[c] += tk[c];
+    if (lane < 16) I.ticks[(size_t)ant * 16 + lane] += tk.v;
   }
 }
 
