@@ -1187,9 +1187,9 @@ constexpr int kChunks = 16;  // 64-element chunks in flight per wave and round
 // Rewrites of more pairs than this (elements, for block moves: twice this)
 // are shared by the team; shorter ones are the leader's alone.
 constexpr int kTeamMinPairs = 256;
-// In a team each wave keeps fewer chunks in flight (the team supplies the
-// rest), which leaves registers for the ant's other state.
-constexpr int kTeamChunks = 8;
+// Chunks in flight per wave of a team rewrite (one round covers
+// TW * kTeamChunks * 64 pairs).
+constexpr int kTeamChunks = 16;
 
 // Reverse the cyclic array range of length L starting at s: pairs (i,
 // L-1-i) are disjoint, so the 64-pair chunks are dealt to the waves of a
