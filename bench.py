@@ -255,7 +255,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(ants shard across GPUs by design, but this build measures one GPU)",
+              "(the ants of an iteration would shard across GPUs; this benchmark "
+              "runs and measures one)",
               file=sys.stderr)
         sys.exit(2)
 
