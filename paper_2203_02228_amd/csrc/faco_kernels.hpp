@@ -589,7 +589,7 @@ FACO_DEV void window_part(const Inst &I, uint64_t t, uint64_t ant, uint64_t step
 // followed to its end, the next one starts from where it stopped (every wave
 // derives the new start alike; the last followed city comes through LDS).
 // Per-wave partial sums of the followed edges end in tl->part.
-constexpr int kWinRounds = 4;
+constexpr int kWinRounds = 16;
 template <int KT, int TW>
 FACO_DEV void window_rounds(const Inst &I, uint64_t t, uint64_t ant, uint64_t step, int u,
                             int pu, int dir, int k, int maxw, int w, TeamLds *tl,
