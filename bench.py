@@ -197,7 +197,7 @@ def run_served_mode(args, quick=False):
             time.sleep(arr - now)
         futs.append(srv.submit(len(futs), p, w.params(), w.iterations))
     for f in futs:
-        f.result()
+        f.result(timeout=args.result_timeout)
     makespan = time.perf_counter() - t0
     srv.close()
     done = sorted(srv.completed, key=lambda r: r.rid)

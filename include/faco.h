@@ -57,6 +57,13 @@ typedef struct faco_params {
   uint64_t seed;         /* Philox4x64-10 key word 0                          */
   uint32_t ls_flags;     /* FACO_LS_* bits                                    */
   int32_t oropt_max_seg; /* longest Or-opt segment; 1..3                      */
+  int32_t min_new_edges_max; /* Alg. 2 calls calc_num_new_edges() once per ant;
+                            0 (or min_new_edges): the constant min_new_edges
+                            of Table 1; above min_new_edges: each ant draws its
+                            threshold uniformly from [min_new_edges,
+                            min_new_edges_max] (Philox counter (iteration,
+                            ant, 0, 3))                                      */
+  int32_t reserved1;     /* must be 0                                         */
 } faco_params;
 
 typedef struct faco_instance faco_instance;
@@ -92,7 +99,8 @@ int faco_run_iterations(faco_instance *h, int32_t iterations);
  * Wait for the handle's stream and copy the global-best tour (n int32 into
  * the caller's host buffer, exactly as stored: tour_out[0] is not rotated)
  * and its cost.  Either pointer may be NULL.
- * Errors: FACO_EINVAL, FACO_EDEVICE.
+ * Errors: FACO_EINVAL; FACO_EDEVICE on a HIP error, or when the device
+ * recorded a fault (FACO_DBG_FAULT; the outputs are still written).
  */
 int faco_get_best_tour(faco_instance *h, int32_t *tour_out,
                        int64_t *length_out);
@@ -167,8 +175,27 @@ enum {
                                [10] copies, [11] backup/nearest choices; call
                                counts: [5] windows, [6] one-step choices, [7]
                                copies, [12] evaluation rounds             */
-  FACO_DBG_TEAM_WAVES = 13  /* int32 [1]: waves per ant of this instance   */
+  FACO_DBG_TEAM_WAVES = 13, /* int32 [1]: waves per ant of this instance   */
+  FACO_DBG_FAULT = 14,      /* int64 [4]: FACO_FAULT_* bits found on the
+                               device, the first fault's ant (-1: initial
+                               solution or global best) and iteration, and
+                               the number of tours verified so far           */
+  FACO_DBG_RECOMPUTED_LENGTHS = 15 /* int64 [n_ants + 1]: runs the tour-length
+                               verification now (Alg. 2's select_shortest
+                               relies on the lengths) and returns every ant's
+                               tour length recomputed from its stored route
+                               and the coordinates, then the global best's;
+                               -1 for an ant route that is not a permutation;
+                               0 for the ants before the first iteration.
+                               A mismatch with the tracked lengths sets a
+                               fault.                                         */
 };
+/* device faults (FACO_DBG_FAULT; faco_get_best_tour then returns
+ * FACO_EDEVICE) */
+#define FACO_FAULT_LS_STALL 1    /* local search stopped early: cities a sweep
+                                    listed had no move in the evaluation    */
+#define FACO_FAULT_LENGTH 2      /* recomputed length != tracked length      */
+#define FACO_FAULT_PERMUTATION 4 /* an ant route is not a permutation        */
 /* per-ant counters (same meaning as the oracle's) */
 enum {
   FACO_CNT_ACO_STEPS = 0,
@@ -191,6 +218,15 @@ int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t bytes);
  * per-ant scratch), for admission by footprint.  Pure arithmetic; valid
  * without a GPU.  Returns 0 for invalid arguments. */
 uint64_t faco_footprint_bytes(int32_t n, const faco_params *p);
+
+/* Tour-length verification in every iteration (Alg. 2's select_shortest
+ * compares the tracked lengths): when enabled, each iteration of
+ * faco_run_iterations and faco_run_batch also recomputes every ant's tour
+ * length and the global best's from the stored tours and the coordinates
+ * (exact int64 sums), checks each ant route against its inverse, and records
+ * a fault on any mismatch (FACO_DBG_FAULT; faco_get_best_tour then fails).
+ * Off by default.  Errors: FACO_EINVAL. */
+int faco_set_verify(faco_instance *h, int32_t enable);
 
 /* Kernel timing.  When enabled, each phase launch of faco_run_iterations is
  * bracketed by HIP events on the handle's stream.  faco_phase_times syncs and

@@ -274,10 +274,30 @@ static int32_t select_next(const orc_instance *h, int32_t u,
  * successor or predecessor there (symmetric TSP).  The closing edge is not
  * counted. */
 
+/* calc_num_new_edges() (Alg. 2): the threshold of one ant's construction,
+ * called once per ant before it starts.  The paper names the function but
+ * states no rule; its experiments use the constant of Table 1.
+ * reading: with min_new_edges_max <= min_new_edges the constant
+ * min_new_edges; otherwise each ant draws its own threshold uniformly from
+ * [min_new_edges, min_new_edges_max]: lo + floor(x * (hi - lo + 1) / 2^64)
+ * with x the Philox word of counter (t, ant, 0, purpose 3). */
+static int32_t calc_num_new_edges(const orc_instance *h, uint64_t t, uint64_t ant) {
+  const int32_t lo = h->m, hi = h->p.min_new_edges_max;
+  if (hi <= lo) return lo;
+  const uint64_t x = draw(h->p.seed, t, ant, 0, ORC_PURPOSE_NEW_EDGES);
+  const uint64_t span = (uint64_t)hi - (uint64_t)lo + 1u;
+  return lo + (int32_t)(((unsigned __int128)x * span) >> 64);
+}
+
+int32_t orc_min_new_edges(const orc_instance *h, uint64_t t, uint64_t ant) {
+  return calc_num_new_edges(h, t, ant);
+}
+
 static int64_t construct(const orc_instance *h, uint64_t t, uint64_t ant,
                          int32_t *route, uint8_t *visited, int32_t *chk,
                          int32_t *nchk, int64_t *cnt) {
   const int32_t n = h->n;
+  const int32_t min_new_edges = calc_num_new_edges(h, t, ant);
   memset(visited, 0, (size_t)n);
   int32_t r0 = uniform_node(draw(h->p.seed, t, ant, 0, ORC_PURPOSE_START), n);
   route[0] = r0;
@@ -296,7 +316,7 @@ static int64_t construct(const orc_instance *h, uint64_t t, uint64_t ant,
       ++new_edges;
       chk[nc++] = v;
     }
-    if (new_edges >= h->m) {
+    if (new_edges >= min_new_edges) {
       int32_t prev = v, c = src_succ(h, v), appended = 0;
       while (!visited[c]) {
         route[k++] = c;
@@ -721,7 +741,8 @@ orc_instance *orc_build(const int32_t *xy, int32_t n, const orc_params *p,
   if (!xy || !p || n < 4 || p->cl_size < 2 || p->bl_size < 0 ||
       p->n_ants < 1 || p->min_new_edges < 0 || !(p->rho >= 0.0f) ||
       !(p->rho < 1.0f) || !(p->p_best > 0.0) || !(p->p_best < 1.0) ||
-      p->oropt_max_seg < 1 || p->oropt_max_seg > 64)
+      p->oropt_max_seg < 1 || p->oropt_max_seg > 64 ||
+      (p->min_new_edges_max > 0 && p->min_new_edges_max < p->min_new_edges))
     return NULL;
   for (int32_t i = 0; i < 2 * n; ++i)
     if (xy[i] < 0 || xy[i] >= (1 << 23)) return NULL;

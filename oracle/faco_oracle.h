@@ -29,6 +29,7 @@ extern "C" {
 #define ORC_PURPOSE_ROULETTE 0u
 #define ORC_PURPOSE_START 1u
 #define ORC_PURPOSE_SOURCE 2u
+#define ORC_PURPOSE_NEW_EDGES 3u
 
 /* per-ant counters */
 enum {
@@ -59,6 +60,9 @@ typedef struct {
   uint64_t seed;         /* Philox key word 0                            */
   uint32_t ls_flags;     /* ORC_LS_* bits                                */
   int32_t oropt_max_seg; /* longest Or-opt segment                       */
+  int32_t min_new_edges_max; /* calc_num_new_edges() range top; <= min_new_edges:
+                                the constant min_new_edges              */
+  int32_t _pad1;
 } orc_params;
 
 typedef struct orc_instance orc_instance;
@@ -100,6 +104,9 @@ void orc_set_pheromone(orc_instance *h, const float *tau);
 int64_t orc_construct(const orc_instance *h, uint64_t t, uint64_t ant,
                       int32_t *route, int32_t *checklist, int32_t *n_check,
                       int64_t *counters);
+
+/* calc_num_new_edges() of Alg. 2 for ant `ant` at iteration t. */
+int32_t orc_min_new_edges(const orc_instance *h, uint64_t t, uint64_t ant);
 
 /* Local search on an arbitrary tour (route in/out); returns total gain. */
 int64_t orc_local_search(const orc_instance *h, int32_t *route,

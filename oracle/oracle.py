@@ -25,7 +25,8 @@ class OrcParams(ctypes.Structure):
                 ("rho", ctypes.c_float), ("_pad0", ctypes.c_float),
                 ("p_best", ctypes.c_double), ("p_source_gbest", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("ls_flags", ctypes.c_uint32),
-                ("oropt_max_seg", ctypes.c_int32)]
+                ("oropt_max_seg", ctypes.c_int32), ("min_new_edges_max", ctypes.c_int32),
+                ("_pad1", ctypes.c_int32)]
 
 
 _lib = None
@@ -69,6 +70,8 @@ def lib():
                                        ctypes.c_uint32, i64p]
         L.orc_nearest_neighbour.restype = ctypes.c_int64
         L.orc_nearest_neighbour.argtypes = [vp, i32p]
+        L.orc_min_new_edges.restype = ctypes.c_int32
+        L.orc_min_new_edges.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64]
         L.orc_best_move_gain.restype = ctypes.c_int64
         L.orc_best_move_gain.argtypes = [vp, i32p, ctypes.c_int32, ctypes.c_uint32]
         L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
@@ -107,9 +110,10 @@ def tour_length(xy, route):
 
 def make_params(cl_size=16, bl_size=64, n_ants=16, min_new_edges=8, rho=0.5,
                 p_best=0.05, p_source_gbest=0.01, seed=1,
-                ls_flags=LS_2OPT | LS_OROPT | LS_SWEEP, oropt_max_seg=3):
+                ls_flags=LS_2OPT | LS_OROPT | LS_SWEEP, oropt_max_seg=3,
+                min_new_edges_max=0):
     return OrcParams(cl_size, bl_size, n_ants, min_new_edges, rho, 0.0, p_best,
-                     p_source_gbest, seed, ls_flags, oropt_max_seg)
+                     p_source_gbest, seed, ls_flags, oropt_max_seg, min_new_edges_max, 0)
 
 
 class Oracle:
@@ -229,6 +233,10 @@ class Oracle:
         r = np.zeros(self.n, dtype=np.int32)
         L = lib().orc_nearest_neighbour(self.h, _p(r, ctypes.c_int32))
         return r, int(L)
+
+    def min_new_edges(self, t, ant):
+        """calc_num_new_edges() of ant `ant` at iteration t."""
+        return int(lib().orc_min_new_edges(self.h, int(t), int(ant)))
 
     def best_move_gain(self, route, a, flags=None):
         r = np.ascontiguousarray(route, dtype=np.int32)

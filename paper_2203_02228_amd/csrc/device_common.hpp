@@ -178,7 +178,12 @@ constexpr uint64_t kM1 = 0xCA5A826395121157ull;
 constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
 
-enum : uint64_t { kPurposeRoulette = 0, kPurposeStart = 1, kPurposeSource = 2 };
+enum : uint64_t {
+  kPurposeRoulette = 0,
+  kPurposeStart = 1,
+  kPurposeSource = 2,
+  kPurposeNewEdges = 3
+};
 
 // Full 128-bit product m * x from four 32 x 32 -> 64 partial products, each
 // with the carry-in folded into its addend (no partial sum overflows 64 bits:

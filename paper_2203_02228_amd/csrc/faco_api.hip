@@ -68,6 +68,10 @@ static const char *validate(const faco_params *p, int32_t n) {
   if (p->bl_size < 0 || p->bl_size > faco::kMaxBl) return "bl_size must be in [0, 64]";
   if (p->n_ants < 1 || p->n_ants > 4096) return "n_ants must be in [1, 4096]";
   if (p->min_new_edges < 0) return "min_new_edges must be >= 0";
+  if (p->min_new_edges_max < 0 ||
+      (p->min_new_edges_max > 0 && p->min_new_edges_max < p->min_new_edges))
+    return "min_new_edges_max must be 0 or >= min_new_edges";
+  if (p->reserved1 != 0) return "reserved1 must be 0";
   if (!(p->rho >= 0.0f) || !(p->rho < 1.0f)) return "rho must be in [0, 1)";
   if (p->reserved0 != 0.0f) return "reserved0 must be 0";
   if (!(p->p_best > 0.0) || !(p->p_best < 1.0)) return "p_best must be in (0, 1)";
@@ -102,6 +106,7 @@ extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
   b += 2 * align_up(4 * N);                   // label maps
   b += 3 * align_up(4 * N * A) + align_up(8 * N * A);  // ant routes, pos, rings, tour coordinates
   b += align_up(8 * A) + 2 * align_up(8 * A * faco::NCNT) + align_up(128 * A);
+  b += 2 * align_up(8 * (A + 1)) + align_up(4 * (A + 1));  // verification
   b += align_up(sizeof(DevState));
   return b;
 }
@@ -190,6 +195,15 @@ static int team_waves_for(int32_t n, int32_t ants) {
   return 1;
 }
 
+// tour-length verification of the ants (ants != 0) and the global best
+static void enqueue_verify(faco_instance *h, int ants, int iter_ahead) {
+  const Inst &I = h->dv;
+  hipLaunchKernelGGL(faco::verify_kernel, dim3(faco::verify_chunks(I.n), (unsigned)I.A + 1),
+                     dim3(faco::kVerifyBlock), 0, h->stream, I, ants);
+  hipLaunchKernelGGL(faco::verify_finish_kernel, dim3(1), dim3(faco::kVerifyBlock), 0,
+                     h->stream, I, ants, iter_ahead);
+}
+
 // enqueue the four phases of one iteration
 static int enqueue_iteration(faco_instance *h) {
   const Inst &I = h->dv;
@@ -205,6 +219,7 @@ static int enqueue_iteration(faco_instance *h) {
     end_timed(h, tl);
     begin_timed(h, 1, tl);
   }
+  if (I.verify) enqueue_verify(h, 1, 1);
   hipLaunchKernelGGL(faco::colony_kernel, dim3(1), dim3(64), 0, h->stream, I);
   if (h->timing) {
     end_timed(h, tl);
@@ -293,6 +308,8 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   I.bl = h->bl;
   I.A = p->n_ants;
   I.m = p->min_new_edges;
+  I.m_hi = p->min_new_edges_max;
+  I.verify = 0;
   I.lcap = queue_lds_cap_for(n);
   I.rho = p->rho;
   I.ls_flags = p->ls_flags;
@@ -337,6 +354,9 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   ALLOC(cnt, int64_t, A * faco::NCNT);
   ALLOC(cnt_acc, int64_t, A * faco::NCNT);
   ALLOC(ticks, int64_t, A * 16);
+  ALLOC(vsum, int64_t, A + 1);
+  ALLOC(vbad, int32_t, A + 1);
+  ALLOC(vout, int64_t, A + 1);
   ALLOC(st, DevState, 1);
 #undef ALLOC
 
@@ -355,6 +375,9 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   BTRY(hipMemsetAsync(I.st, 0, sizeof(DevState), h->stream));
   BTRY(hipMemsetAsync(I.cnt_acc, 0, sizeof(int64_t) * A * faco::NCNT, h->stream));
   BTRY(hipMemsetAsync(I.ticks, 0, sizeof(int64_t) * A * 16, h->stream));
+  BTRY(hipMemsetAsync(I.vsum, 0, sizeof(int64_t) * (A + 1), h->stream));
+  BTRY(hipMemsetAsync(I.vbad, 0, sizeof(int32_t) * (A + 1), h->stream));
+  BTRY(hipMemsetAsync(I.vout, 0, sizeof(int64_t) * (A + 1), h->stream));
   hilbert_labels(xy, n, h->orig_of, h->int_of);
   std::vector<int32_t> xy_int(2 * N);
   for (size_t i = 0; i < N; ++i) {
@@ -441,6 +464,26 @@ static hipError_t d2h(faco_instance *h, void *dst, const void *src, size_t bytes
   return hipStreamSynchronize(h->stream);
 }
 
+static int fault_error(faco_instance *h, const DevState &hs) {
+  std::string what;
+  if (hs.fault & faco::FAULT_LS_STALL)
+    what += " local search stopped: a sweep listed cities that the move evaluation found no"
+            " move for;";
+  if (hs.fault & faco::FAULT_LENGTH)
+    what += " a recomputed tour length differs from the tracked one;";
+  if (hs.fault & faco::FAULT_PERMUTATION) what += " an ant's route is not a permutation;";
+  return set_err(h, FACO_EDEVICE,
+                 "device fault" + what + " first at ant " + std::to_string(hs.fault_ant) +
+                     " (-1: initial solution or global best), iteration " +
+                     std::to_string(hs.fault_iter));
+}
+
+extern "C" int faco_set_verify(faco_instance *h, int32_t enable) {
+  if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
+  h->dv.verify = enable ? 1 : 0;
+  return FACO_OK;
+}
+
 extern "C" int faco_get_best_tour(faco_instance *h, int32_t *tour_out, int64_t *length_out) {
   if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -448,11 +491,10 @@ extern "C" int faco_get_best_tour(faco_instance *h, int32_t *tour_out, int64_t *
     HIP_TRY(h, d2h(h, tour_out, h->dv.gb_route, sizeof(int32_t) * (size_t)h->n));
     for (int32_t i = 0; i < h->n; ++i) tour_out[i] = h->orig_of[(size_t)tour_out[i]];
   }
-  if (length_out) {
-    DevState hs;
-    HIP_TRY(h, d2h(h, &hs, h->dv.st, sizeof(DevState)));
-    *length_out = hs.gb_len;
-  }
+  DevState hs;
+  HIP_TRY(h, d2h(h, &hs, h->dv.st, sizeof(DevState)));
+  if (length_out) *length_out = hs.gb_len;
+  if (hs.fault) return fault_error(h, hs);
   return FACO_OK;
 }
 
@@ -504,6 +546,22 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
       if (bytes != 64) return set_err(h, FACO_EINVAL, "size mismatch");
       int64_t v[8] = {hs.iter, h->k, h->bl, hs.ib, hs.src_gb, hs.init_len, hs.gb_len, hs.src_len};
       std::memcpy(out, v, 64);
+      return FACO_OK;
+    }
+    case FACO_DBG_FAULT: {
+      if (bytes != 32) return set_err(h, FACO_EINVAL, "size mismatch");
+      int64_t v[4] = {hs.fault, hs.fault_ant, hs.fault_iter, hs.verified};
+      std::memcpy(out, v, 32);
+      return FACO_OK;
+    }
+    case FACO_DBG_RECOMPUTED_LENGTHS: {
+      if (bytes != 8 * (A + 1)) return set_err(h, FACO_EINVAL, "size mismatch");
+      // ant tours exist once an iteration has run
+      enqueue_verify(h, hs.iter > 0 ? 1 : 0, 0);
+      HIP_TRY(h, hipGetLastError());
+      HIP_TRY(h, d2h(h, out, h->dv.vout, 8 * (A + 1)));
+      if (hs.iter == 0)
+        for (size_t a = 0; a < A; ++a) ((int64_t *)out)[a] = 0;
       return FACO_OK;
     }
     case FACO_DBG_TEAM_WAVES: {
@@ -621,13 +679,16 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
   // host tables
   std::vector<Inst> insts(count);
   std::vector<int2> amap;
-  int kmax = 2, maxn = 0;
+  int kmax = 2, maxn = 0, max_ants = 0;
+  bool any_verify = false;
   size_t lds_words = 0, max_slots = 0;
   for (int32_t i = 0; i < count; ++i) {
     faco_instance *h = hs[i];
     insts[i] = h->dv;
     kmax = h->k > kmax ? h->k : kmax;
     maxn = h->n > maxn ? h->n : maxn;
+    max_ants = h->p.n_ants > max_ants ? h->p.n_ants : max_ants;
+    any_verify = any_verify || h->dv.verify;
     const size_t words = 3 * (size_t)((h->n + 31) / 32) + (size_t)h->dv.lcap;
     lds_words = words > lds_words ? words : lds_words;
     const size_t slots = (size_t)h->n * (size_t)h->k;
@@ -685,6 +746,14 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
   auto enqueue = [&](hipStream_t s) {
     hipLaunchKernelGGL(antk, dim3(nb_ant), dim3(64 * (tw > 1 ? tw : apb)), lds_bytes, s,
                        g_ws.insts, g_ws.amap, total, apb, (int)lds_words);
+    if (any_verify) {
+      hipLaunchKernelGGL(faco::verify_batch_kernel,
+                         dim3(faco::verify_chunks(maxn), (unsigned)max_ants + 1,
+                              (unsigned)count),
+                         dim3(faco::kVerifyBlock), 0, s, (const Inst *)g_ws.insts);
+      hipLaunchKernelGGL(faco::verify_finish_batch_kernel, dim3((unsigned)count),
+                         dim3(faco::kVerifyBlock), 0, s, (const Inst *)g_ws.insts);
+    }
     hipLaunchKernelGGL(faco::colony_batch_kernel, dim3((unsigned)count), dim3(64), 0, s,
                        (const Inst *)g_ws.insts);
     hipLaunchKernelGGL(faco::source_batch_kernel, g_src, dim3(256), 0, s,

@@ -143,6 +143,81 @@ __global__ void init_state_kernel(Inst I) {
 
 
 // ===================================================================== //
+// Tour-length verification: every ant's tour (when `ants` is set) and the
+// global best are summed again from the stored tours and the coordinates
+// (int64, exact), and each ant's route is checked against its inverse
+// (route[pos[c]] = c for every position: a permutation).  The sums are
+// compared with the lengths the construction and local search tracked; a
+// mismatch sets a fault.  Partial sums accumulate in vsum/vbad (zero
+// between verifications; the finishing kernel reads and clears them).
+//   verify: grid (chunks, A + 1 tours), block kVerifyBlock
+// ===================================================================== //
+constexpr int kVerifyBlock = 256;
+
+FACO_DEV void verify_part(const Inst &I, int tour, int ants, int chunk, int nchunks) {
+  const int n = I.n;
+  const bool gb = tour == I.A;
+  if (!gb && !ants) return;
+  const int32_t *r = gb ? I.gb_route : I.routes + (size_t)tour * (size_t)n;
+  const int32_t *pos = gb ? nullptr : I.pos + (size_t)tour * (size_t)n;
+  int64_t s = 0;
+  bool bad = false;
+  for (int i = chunk * kVerifyBlock + (int)threadIdx.x; i < n; i += nchunks * kVerifyBlock) {
+    const int c = r[i], d = r[i + 1 == n ? 0 : i + 1];
+    if ((unsigned)c >= (unsigned)n || (unsigned)d >= (unsigned)n) {
+      bad = true;
+      continue;
+    }
+    if (pos && pos[c] != i) bad = true;
+    s += cost(I.xy[c], I.xy[d]);
+  }
+  s = wave_sum_i64(s);
+  const bool wbad = ballot(bad) != 0;
+  if (lane_id() == 0) {
+    if (s) atomicAdd((unsigned long long *)&I.vsum[tour], (unsigned long long)s);
+    if (wbad) atomicOr(&I.vbad[tour], 1);
+  }
+}
+
+// Compare, publish the recomputed lengths in vout, clear the partial sums.
+// iter_ahead: 1 when the ants being checked belong to the iteration in
+// progress (before the colony update counts it), else 0.
+FACO_DEV void verify_finish(const Inst &I, int ants, int iter_ahead) {
+  DevState *st = I.st;
+  for (int t = (int)threadIdx.x; t <= I.A; t += (int)blockDim.x) {
+    if (t < I.A && !ants) continue;
+    const int64_t L = I.vsum[t];
+    const bool bad = I.vbad[t] != 0;
+    const int64_t want = t < I.A ? I.lens[t] : st->gb_len;
+    I.vout[t] = bad ? -1 : L;
+    if (bad || L != want) {
+      const int32_t bit = bad ? FAULT_PERMUTATION : FAULT_LENGTH;
+      if (atomicOr(&st->fault, bit) == 0) {
+        st->fault_ant = t < I.A ? t : -1;
+        st->fault_iter = st->iter + iter_ahead;
+      }
+    }
+    I.vsum[t] = 0;
+    I.vbad[t] = 0;
+  }
+  if (threadIdx.x == 0) st->verified += (ants ? I.A : 0) + 1;
+}
+
+__global__ void __launch_bounds__(kVerifyBlock) verify_kernel(Inst I, int ants) {
+  verify_part(I, (int)blockIdx.y, ants, (int)blockIdx.x, (int)gridDim.x);
+}
+__global__ void __launch_bounds__(kVerifyBlock) verify_finish_kernel(Inst I, int ants,
+                                                                     int iter_ahead) {
+  verify_finish(I, ants, iter_ahead);
+}
+
+// chunks per tour of a verification launch
+__host__ __device__ inline unsigned verify_chunks(int n) {
+  const int c = (n + 4 * kVerifyBlock - 1) / (4 * kVerifyBlock);
+  return (unsigned)(c < 1 ? 1 : (c > 128 ? 128 : c));
+}
+
+// ===================================================================== //
 // Batched forms: blockIdx selects the instance; each instance reads only
 // its own Inst.
 // ===================================================================== //
@@ -157,6 +232,20 @@ __global__ void __launch_bounds__(256) source_batch_kernel(const Inst *insts) {
 
 __global__ void __launch_bounds__(256) pheromone_batch_kernel(const Inst *insts) {
   run_pheromone(insts[blockIdx.y], (size_t)blockIdx.x * blockDim.x + threadIdx.x, 0);
+}
+
+// blockIdx.z = instance; instances without verification, and tours or
+// chunks past an instance's own, return
+__global__ void __launch_bounds__(kVerifyBlock) verify_batch_kernel(const Inst *insts) {
+  const Inst &I = insts[blockIdx.z];
+  if (!I.verify || (int)blockIdx.y > I.A) return;
+  const unsigned nc = verify_chunks(I.n);
+  if (blockIdx.x >= nc) return;
+  verify_part(I, (int)blockIdx.y, 1, (int)blockIdx.x, (int)nc);
+}
+__global__ void __launch_bounds__(kVerifyBlock) verify_finish_batch_kernel(const Inst *insts) {
+  const Inst &I = insts[blockIdx.x];
+  if (I.verify) verify_finish(I, 1, 1);
 }
 
 // ===================================================================== //

@@ -17,6 +17,21 @@ struct DevState {
   int32_t improved;  // 1 if the last iteration improved the global best
   int32_t dup;       // set by the list kernel when two cities coincide
   int64_t init_cnt[12];
+  // Faults found on the device (FAULT_* bits; the first one's ant and
+  // iteration), and the number of tours the verification kernel has checked.
+  int32_t fault, fault_ant;
+  int64_t fault_iter;
+  int64_t verified;
+};
+
+enum : int32_t {
+  // a sweep listed cities with improving moves, but their evaluation found
+  // no move (the two move tests disagree): the local search stopped early
+  FAULT_LS_STALL = 1,
+  // a recomputed tour length differs from the incrementally tracked one
+  FAULT_LENGTH = 2,
+  // an ant's route is not a permutation (route and pos disagree)
+  FAULT_PERMUTATION = 4,
 };
 
 // Device view of one instance (kernel argument).  Layouts:
@@ -30,6 +45,8 @@ struct DevState {
 //   cnt_acc   int64 [A][12]      the same summed over all iterations
 struct Inst {
   int32_t n, k, bl, A, m;
+  int32_t m_hi;       // calc_num_new_edges() range top (<= m: the constant m)
+  int32_t verify;     // 1: each iteration recomputes and checks tour lengths
   int32_t lcap;       // capacity of the LDS part of an ant's work queue
   float rho;
   uint32_t ls_flags;
@@ -65,6 +82,11 @@ struct Inst {
   int2 *rxy;          // [A][n] coordinates of routes[a][p] (tour order)
   int64_t *lens, *cnt, *cnt_acc;
   int64_t *ticks;     // [A][16] wall-clock ticks and call counts per phase, summed
+  // tour-length verification: partial sums and route faults of the tours
+  // being checked (ants 0..A-1, then the global best), the last results
+  int64_t *vsum;      // [A + 1], zero between verifications
+  int32_t *vbad;      // [A + 1], zero between verifications
+  int64_t *vout;      // [A + 1] recomputed lengths (-1: not a permutation)
   DevState *st;
 };
 

@@ -728,6 +728,13 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
                                      n)]);
   int u = r0;
   append_city(I, u, 0, route, pos, rxy, vis);
+  // calc_num_new_edges() (Alg. 2): the constant min_new_edges, or this ant's
+  // uniform draw from [min_new_edges, min_new_edges_max]
+  int m = I.m;
+  if (!greedy && I.m_hi > I.m)
+    m += (int)__umul64hi(philox_word0(I.seed, t, (uint64_t)ant, 0, kPurposeNewEdges),
+                         (uint64_t)(I.m_hi - I.m) + 1u);
+  m = uniform_i(m);
   int k = 1, new_edges = 0;
   nchk = 0;
   int64_t len = 0;
@@ -760,7 +767,7 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
       pu = uniform_i(pu);
       dir = uniform_i(dir);
       step = uniform_u64(step);
-      const int maxw = new_edges >= I.m ? 1 : TW * kWave;
+      const int maxw = new_edges >= m ? 1 : TW * kWave;
       int v, dv = 0, pv = 0;
       const int64_t c0 = ticks();
       if (maxw == 1) {
@@ -818,7 +825,7 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
       new_edges = uniform_i(new_edges);
       k = uniform_i(k);
       dir = uniform_i(dir);
-      if (new_edges >= I.m && k < n) {
+      if (new_edges >= m && k < n) {
         const int64_t c2 = ticks();
         const int app = copy_from<TW>(I, pv, k, u, pu, len, tl, route, pos, rxy, vis);
         cnt[CNT_COPIED] += app;
@@ -1570,11 +1577,22 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
   return pushed;
 }
 
+// The first fault of the instance keeps its ant (-1: the initial solution)
+// and the iteration being built.
+FACO_DEV void record_fault(const Inst &I, int32_t bit, int ant) {
+  if (lane_id() == 0) {
+    if (atomicOr(&I.st->fault, bit) == 0) {
+      I.st->fault_ant = ant;
+      I.st->fault_iter = I.st->iter + 1;
+    }
+  }
+}
+
 template <int KT, int TW>
 FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                               int32_t *pos, int2 *rxy, uint32_t *inq, uint32_t *touched,
                               uint32_t *ord, TeamLds *tl, int W, Queue Q, LaneCounters &cnt,
-                              LaneCounters &tk) {
+                              LaneCounters &tk, int ant) {
   constexpr int GS = KT <= 16 ? 16 : 32;  // lanes per evaluated city
   constexpr int G = kWave / GS;           // cities evaluated together
   const int n = I.n, lane = lane_id();
@@ -1661,9 +1679,12 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     changes = uniform_i(changes);
     if (!(flags & LS_SWEEP) || changes >= n) break;
     // Every city a sweep lists has an improving move, so a sweep that was
-    // followed by no change can only come from the two evaluators disagreeing;
-    // stop instead of spinning.
-    if (changes == changes_at_sweep) break;
+    // followed by no change can only come from the two move tests
+    // disagreeing: stop instead of spinning, and report it.
+    if (changes == changes_at_sweep) {
+      record_fault(I, FAULT_LS_STALL, ant);
+      break;
+    }
     changes_at_sweep = changes;
     cnt[CNT_SWEEPS]++;
     const int64_t t2 = ticks();
@@ -1794,7 +1815,8 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   Q.cap = uniform_i(Q.cap);
   Q.in_lds = uniform_i(Q.in_lds);
   if (flags & (LS_2OPT | LS_OROPT))
-    len -= local_search<KT, TW>(I, flags, route, pos, rxy, inq, vis, ord, tl, W, Q, cnt, tk);
+    len -= local_search<KT, TW>(I, flags, route, pos, rxy, inq, vis, ord, tl, W, Q, cnt, tk,
+                                init ? -1 : ant);
   if (TW > 1) {
     if (lane == 0) tl->op = OP_EXIT;
     team_sync();

@@ -18,7 +18,9 @@ FACO_LS_2OPT, FACO_LS_OROPT, FACO_LS_SWEEP = 1, 2, 4
 (FACO_DBG_ANT_ROUTES, FACO_DBG_ANT_LENGTHS, FACO_DBG_PHEROMONE, FACO_DBG_SOURCE,
  FACO_DBG_LIMITS, FACO_DBG_COUNTERS, FACO_DBG_CAND_LISTS, FACO_DBG_BACKUP_LISTS,
  FACO_DBG_HEURISTIC, FACO_DBG_INFO, FACO_DBG_INIT_COUNTERS,
- FACO_DBG_COUNTER_TOTALS, FACO_DBG_PHASE_TICKS, FACO_DBG_TEAM_WAVES) = range(14)
+ FACO_DBG_COUNTER_TOTALS, FACO_DBG_PHASE_TICKS, FACO_DBG_TEAM_WAVES, FACO_DBG_FAULT,
+ FACO_DBG_RECOMPUTED_LENGTHS) = range(16)
+FACO_FAULT_LS_STALL, FACO_FAULT_LENGTH, FACO_FAULT_PERMUTATION = 1, 2, 4
 CNT_NAMES = ["aco_steps", "copied", "backup", "fallback", "new_edges",
              "ls_pops", "moves_2opt", "moves_oropt", "moved_elems", "sweeps",
              "checklist0", "ls_gain"]
@@ -28,7 +30,7 @@ EXPORTED = ["faco_build_instance", "faco_run_iterations", "faco_get_best_tour",
             "faco_destroy_instance", "faco_last_error", "faco_run_batch",
             "faco_debug_get", "faco_footprint_bytes", "faco_set_timing",
             "faco_phase_times", "faco_set_batch_ants_per_block", "faco_set_team_waves",
-            "faco_set_queue_lds_capacity"]
+            "faco_set_queue_lds_capacity", "faco_set_verify"]
 
 
 class faco_params(ctypes.Structure):
@@ -37,7 +39,8 @@ class faco_params(ctypes.Structure):
                 ("rho", ctypes.c_float), ("reserved0", ctypes.c_float),
                 ("p_best", ctypes.c_double), ("p_source_gbest", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("ls_flags", ctypes.c_uint32),
-                ("oropt_max_seg", ctypes.c_int32)]
+                ("oropt_max_seg", ctypes.c_int32), ("min_new_edges_max", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32)]
 
 
 class FacoError(RuntimeError):
@@ -89,6 +92,8 @@ def lib():
         L.faco_set_team_waves.argtypes = [ctypes.c_int32]
         L.faco_set_queue_lds_capacity.restype = ctypes.c_int
         L.faco_set_queue_lds_capacity.argtypes = [ctypes.c_int32]
+        L.faco_set_verify.restype = ctypes.c_int
+        L.faco_set_verify.argtypes = [vp, ctypes.c_int32]
         L.faco_phase_times.restype = ctypes.c_int
         L.faco_phase_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         _lib = L
@@ -98,9 +103,9 @@ def lib():
 def make_params(cl_size=16, bl_size=64, n_ants=16, min_new_edges=8, rho=0.5,
                 p_best=0.05, p_source_gbest=0.01, seed=1,
                 ls_flags=FACO_LS_2OPT | FACO_LS_OROPT | FACO_LS_SWEEP,
-                oropt_max_seg=3):
+                oropt_max_seg=3, min_new_edges_max=0):
     return faco_params(cl_size, bl_size, n_ants, min_new_edges, rho, 0.0, p_best,
-                       p_source_gbest, seed, ls_flags, oropt_max_seg)
+                       p_source_gbest, seed, ls_flags, oropt_max_seg, min_new_edges_max, 0)
 
 
 def _check(rc, h=None):
@@ -198,6 +203,11 @@ def faco_set_timing(inst, enable=True):
     _check(lib().faco_set_timing(inst.h, 1 if enable else 0), inst.h)
 
 
+def faco_set_verify(inst, enable=True):
+    """Recompute and check every tour length in each later iteration."""
+    _check(lib().faco_set_verify(inst.h, 1 if enable else 0), inst.h)
+
+
 def faco_phase_times(inst):
     ms = (ctypes.c_double * 4)()
     cnt = (ctypes.c_int64 * 4)()
@@ -224,6 +234,8 @@ def faco_debug_get(inst, what):
         FACO_DBG_COUNTER_TOTALS: (np.int64, (A, FACO_NCNT)),
         FACO_DBG_PHASE_TICKS: (np.int64, (A, 16)),
         FACO_DBG_TEAM_WAVES: (np.int32, (1,)),
+        FACO_DBG_FAULT: (np.int64, (4,)),
+        FACO_DBG_RECOMPUTED_LENGTHS: (np.int64, (A + 1,)),
     }
     dt, shape = shapes[what]
     out = np.zeros(shape, dtype=dt)

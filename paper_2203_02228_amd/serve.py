@@ -144,9 +144,35 @@ class Server:
                     self.ready[self._class_of(len(r.xy))].append(r)
                     self.lock.notify_all()
             except Exception as e:  # report and free the slot
-                r.future.set_exception(e)
-                self.errors.append((r.rid, repr(e)))
-                self._release(r)
+                self._fail(r, e)
+
+    def _fail(self, r, exc):
+        """Resolve r's future with exc, free its device state and footprint."""
+        if not r.future.done():
+            r.future.set_exception(exc)
+        self.errors.append((r.rid, repr(exc)))
+        h, r.handle = r.handle, None
+        if h is not None:
+            try:
+                h.close()
+            except Exception as e:  # the slot is released regardless
+                self.errors.append((r.rid, "close: " + repr(e)))
+        self._release(r)
+
+    def _retire(self, r):
+        """Read back a finished solve, free it and resolve its future."""
+        try:
+            tour, length = F.faco_get_best_tour(r.handle)
+            r.finished = time.perf_counter()
+            r.result = (tour, length)
+            h, r.handle = r.handle, None
+            h.close()
+        except Exception as e:
+            self._fail(r, e)
+            return
+        self.completed.append(r)
+        r.future.set_result((tour, length))
+        self._release(r)
 
     def _worker(self, c):
         stream = self.run_streams[c]
@@ -159,14 +185,14 @@ class Server:
                     return
                 while self.ready[c]:
                     active.append(self.ready[c].popleft())
-            steps = min(self.chunk, min(r.iterations - r.done_iters for r in active))
             try:
+                steps = min(self.chunk, min(r.iterations - r.done_iters for r in active))
                 F.faco_run_batch([r.handle for r in active], steps, stream=stream)
                 stream.synchronize()
             except Exception as e:
+                # every resident solve of the class fails with the batch
                 for r in active:
-                    r.future.set_exception(e)
-                    self._release(r)
+                    self._fail(r, e)
                 self.errors.append(("batch", repr(e)))
                 active = []
                 continue
@@ -174,14 +200,7 @@ class Server:
             for r in active:
                 r.done_iters += steps
                 if r.done_iters >= r.iterations:
-                    tour, length = F.faco_get_best_tour(r.handle)
-                    r.finished = time.perf_counter()
-                    r.result = (tour, length)
-                    r.handle.close()
-                    r.handle = None
-                    self.completed.append(r)
-                    r.future.set_result((tour, length))
-                    self._release(r)
+                    self._retire(r)
                 else:
                     keep.append(r)
             active = keep

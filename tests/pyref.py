@@ -27,12 +27,13 @@ def dist(xy, i, j):
 class Ref:
     def __init__(self, xy, cl_size=16, bl_size=64, n_ants=4, min_new_edges=8,
                  rho=0.5, p_best=0.05, p_source_gbest=0.01, seed=1,
-                 ls_flags=7, oropt_max_seg=3):
+                 ls_flags=7, oropt_max_seg=3, min_new_edges_max=0):
         self.xy = [(int(a), int(b)) for a, b in xy]
         n = self.n = len(xy)
         self.k = min(cl_size, n - 1)
         self.bl = min(bl_size, n - 1 - self.k)
         self.A, self.m = n_ants, min_new_edges
+        self.m_hi = min_new_edges_max
         self.rho = np.float32(rho)
         self.p_best, self.p_gb, self.seed = p_best, p_source_gbest, seed
         self.flags, self.maxseg = ls_flags, oropt_max_seg
@@ -112,12 +113,22 @@ class Ref:
                    key=lambda j: ((self.xy[u][0] - self.xy[j][0]) ** 2 +
                                   (self.xy[u][1] - self.xy[j][1]) ** 2, j))
 
+    def threshold(self, t, ant):
+        """Alg. 2's calc_num_new_edges(): the constant, or a uniform integer
+        in [min_new_edges, min_new_edges_max] from the Philox word of
+        (t, ant, 0, 3)."""
+        if self.m_hi <= self.m:
+            return self.m
+        x = philox_word0(self.seed, (t, ant, 0, 3))
+        return self.m + (x * (self.m_hi - self.m + 1) >> 64)
+
     def construct(self, t, ant):
         n = self.n
         x = philox_word0(self.seed, (t, ant, 0, 1))
         r0 = (x * n) >> 64
         route, vis, chk = [r0], {r0}, []
         new, step = 0, 0
+        m = self.threshold(t, ant)
         while len(route) < n:
             u = route[-1]
             v = self.choose(u, vis, t, ant, step)
@@ -127,7 +138,7 @@ class Ref:
             if v != self.s_succ(u) and v != self.s_pred(u):
                 new += 1
                 chk.append(v)
-            if new >= self.m:
+            if new >= m:
                 c, app = self.s_succ(v), 0
                 while c not in vis:
                     route.append(c)

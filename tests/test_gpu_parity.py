@@ -62,6 +62,7 @@ def _cmp_iter(o, g, it):
     bt, bl = F.faco_get_best_tour(g)
     ot, ol = o.best()
     assert bl == ol and np.array_equal(bt, ot), it
+    assert F.faco_debug_get(g, F.FACO_DBG_FAULT)[0] == 0, it
 
 
 SMALL = [
@@ -75,6 +76,8 @@ SMALL = [
     (65, "uniform", 7, dict(n_ants=8, min_new_edges=3, cl_size=6, bl_size=0)),
     (130, "cluster16", 8, dict(n_ants=8, min_new_edges=4, ls_flags=0)),
     (257, "uniform", 9, dict(n_ants=7, min_new_edges=6, rho=0.9, p_source_gbest=0.5)),
+    # calc_num_new_edges() drawn per ant from a range
+    (300, "cluster16", 10, dict(n_ants=9, min_new_edges=2, min_new_edges_max=25)),
 ]
 
 

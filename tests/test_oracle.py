@@ -197,7 +197,7 @@ def _check_construction(o, t, ant):
     steps = cnt[0]
     copied = cnt[1]
     assert steps + copied == n - 1
-    m = o.params.min_new_edges
+    m = o.min_new_edges(t, ant)
     if copied > 0:
         assert len(new) >= m
     return route, chk, cnt
@@ -212,6 +212,65 @@ def test_construction_invariants(m):
         route, chk, cnt = _check_construction(o, 4, ant)
         if m >= o.n:
             assert cnt[1] == 0                     # pure ACO: nothing copied
+
+
+def _numpy_philox_word0(seed, ctr):
+    c = sum(int(v) << (64 * i) for i, v in enumerate(ctr))
+    return int(np.random.Philox(counter=(c - 1) % (1 << 256), key=int(seed)).random_raw(1)[0])
+
+
+def test_new_edge_threshold_draws_match_numpy_philox():
+    """calc_num_new_edges() with a range: lo + floor(x (hi - lo + 1) / 2^64),
+    x = word 0 of Philox4x64-10 at counter (t, ant, 0, 3), recomputed here from
+    numpy's own generator."""
+    xy = I.uniform(60, 3)
+    lo, hi, seed = 5, 20, 11
+    o = O.Oracle(xy, n_ants=4, min_new_edges=lo, min_new_edges_max=hi, seed=seed)
+    for t in range(1, 30):
+        for ant in range(0, 40, 3):
+            x = _numpy_philox_word0(seed, (t, ant, 0, 3))
+            assert o.min_new_edges(t, ant) == lo + ((x * (hi - lo + 1)) >> 64)
+
+
+def test_new_edge_threshold_uniform():
+    """The per-ant thresholds are uniform over [lo, hi] (chi-square, 16 cells)."""
+    xy = I.uniform(60, 4)
+    lo, hi = 8, 23
+    o = O.Oracle(xy, n_ants=4, min_new_edges=lo, min_new_edges_max=hi)
+    draws = np.array([o.min_new_edges(t, a) for t in range(1, 401) for a in range(50)])
+    assert draws.min() >= lo and draws.max() <= hi
+    cnt = np.bincount(draws - lo, minlength=hi - lo + 1)
+    exp = len(draws) / (hi - lo + 1)
+    chi2 = float(((cnt - exp) ** 2 / exp).sum())
+    assert chi2 < 37.7          # 15 dof, p = 0.001
+
+
+def test_new_edge_threshold_empty_range_is_table1_constant():
+    """min_new_edges_max = 0 or = min_new_edges reduces calc_num_new_edges() to the
+    constant of Table 1: the whole run is identical to one without a range."""
+    xy = I.make_points("cluster16", 400, 5)
+    runs = []
+    for top in (0, 6):
+        o = O.Oracle(xy, n_ants=6, min_new_edges=6, min_new_edges_max=top)
+        assert all(o.min_new_edges(t, a) == 6 for t in range(1, 5) for a in range(6))
+        o.run(4)
+        runs.append((o.ant_routes(), o.pheromone(), o.best()[1]))
+    for r in runs[1:]:
+        assert np.array_equal(r[0], runs[0][0]) and np.array_equal(r[1], runs[0][1])
+        assert r[2] == runs[0][2]
+
+
+def test_construction_with_threshold_range():
+    """Each ant stops constructing by Eq. (1) once its own threshold is
+    reached: counted new edges >= that ant's draw whenever it copied."""
+    xy = I.make_points("cluster16", 800, 22)
+    o = O.Oracle(xy, n_ants=8, min_new_edges=2, min_new_edges_max=40, rho=0.5)
+    o.run(2)
+    ms = set()
+    for ant in range(30):
+        route, chk, cnt = _check_construction(o, 3, ant)
+        ms.add(o.min_new_edges(3, ant))
+    assert len(ms) > 10
 
 
 def test_copy_reproduces_source_when_pheromone_is_decisive():

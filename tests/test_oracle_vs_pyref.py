@@ -18,6 +18,8 @@ CASES = [
                             ls_flags=O.LS_2OPT)),
     (33, "uniform", 6, dict(cl_size=7, bl_size=5, n_ants=4, min_new_edges=5, rho=0.5,
                             ls_flags=O.LS_OROPT | O.LS_SWEEP, oropt_max_seg=2)),
+    (34, "cluster16", 7, dict(cl_size=6, bl_size=4, n_ants=5, min_new_edges=1, rho=0.4,
+                              min_new_edges_max=9)),
 ]
 
 

@@ -73,3 +73,56 @@ def test_oversized_request_rejected(monkeypatch):
     with pytest.raises(F.FacoError):
         fut.result(timeout=5)
     srv.close()
+
+
+def test_failed_readback_resolves_every_future(monkeypatch):
+    """A device error while retiring one solve fails that request only: every
+    future resolves, the failed solve's handle is closed and its footprint is
+    released, and the worker keeps serving the others."""
+    log = []
+    F, S = _fake_modules(monkeypatch, log)
+
+    def get_best(h):
+        if h.n == 6:
+            raise F.FacoError(F.FACO_EDEVICE, "read-back failed")
+        return np.arange(h.n), h.n * 10 + h.it
+    monkeypatch.setattr(F, "faco_get_best_tour", get_best)
+    srv = S.Server(hbm_budget_bytes=10_000, chunk=4, classes=(50, 1 << 30), builders=2)
+    sizes = [4, 6, 5, 9, 3]
+    futs = [srv.submit(i, np.zeros((n, 2), np.int32), {}, 10) for i, n in enumerate(sizes)]
+    for n, f in zip(sizes, futs):
+        if n == 6:
+            with pytest.raises(F.FacoError):
+                f.result(timeout=20)
+        else:
+            assert f.result(timeout=20)[1] == n * 10 + 10
+    srv.close()
+    assert srv.used == 0
+    assert sorted(e[1] for e in log if e[0] == "close") == sorted(sizes)
+    assert any(rid == 1 for rid, _ in srv.errors)
+
+
+def test_failed_batch_resolves_every_future(monkeypatch):
+    """A batch launch that fails fails every solve resident in it: all futures
+    resolve with the error, all handles are closed, the budget is free again,
+    and later requests are still served."""
+    log = []
+    F, S = _fake_modules(monkeypatch, log)
+    calls = [0]
+
+    def run_batch(hs, steps, stream=None):
+        calls[0] += 1
+        if calls[0] == 1:
+            raise F.FacoError(F.FACO_EDEVICE, "launch failed")
+        for h in hs:
+            h.it += steps
+    monkeypatch.setattr(F, "faco_run_batch", run_batch)
+    srv = S.Server(hbm_budget_bytes=100_000, chunk=4, classes=(1 << 30,), builders=1)
+    first = srv.submit(0, np.zeros((7, 2), np.int32), {}, 8)
+    with pytest.raises(F.FacoError):
+        first.result(timeout=20)
+    later = srv.submit(1, np.zeros((5, 2), np.int32), {}, 8)
+    assert later.result(timeout=20)[1] == 5 * 10 + 8
+    srv.close()
+    assert srv.used == 0
+    assert sorted(e[1] for e in log if e[0] == "close") == [5, 7]
