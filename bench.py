@@ -2,11 +2,30 @@
 
 A step is one iteration of the FACO main loop over the whole colony: every ant
 builds its focused tour and improves it with 2-opt/Or-opt, then the colony
-update and the pheromone update run.  The default workload is the 100 000-city
-stipple-like instance (64 ants, 32 new edges, retention 0.5, k = 16,
-backup lists of 64).  Prints one JSON line.
+update and the pheromone update run.  The workload is the 100 000-city
+stipple-like instance (64 ants, 32 new edges, retention 0.5, k = 16, backup
+lists of 64).  Prints one JSON line on stdout (progress goes to stderr).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+The line's `value` is the rate of the K timed iterations that follow W
+untimed ones.  Beside it the line carries:
+  full_run        the configured run (1000 iterations from the build) timed
+                  on a fresh instance, every tour length recomputed and
+                  checked on the device in every iteration;
+  lengths_verified  the timed instance's tours recomputed after the region;
+  roofline        the ant kernel against HBM bandwidth, algorithmic bytes from
+                  the per-ant counters (the byte model below) over the mean
+                  ant-kernel launch time taken with HIP events in the timed
+                  region; traffic from the committed counter profile when it
+                  was taken on this kernel source and window;
+  cpu_baseline    the oracle on the host over the same iterations, with
+                  threads = min(nproc, ants), plus one-thread and smaller-
+                  workload figures;
+  batched, served short runs of the 256-instance batch and of the 256-request
+                  Poisson stream (--no-batch / --no-served to skip).
+
+    python bench.py --workload batch256 | served   runs only that mode.
 """
 import argparse
 import json
@@ -22,6 +41,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     import hashlib
     import glob
@@ -35,9 +58,9 @@ def kernel_source_hash():
 def profiled_traffic(workload, warmup, steps):
     """HBM bytes per ant-kernel launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, if it was taken on this kernel source over this window."""
-    path = os.path.join(ROOT, "profiles", f"ant_kernel_{workload}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"ant_kernel_{workload}_w{warmup}_s{steps}_traffic.md")
     if not os.path.exists(path):
-        return None
+        return None, "no committed counter profile for this window"
     kv = {}
     with open(path) as f:
         for line in f:
@@ -45,34 +68,46 @@ def profiled_traffic(workload, warmup, steps):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("source_hash") != kernel_source_hash():
-        return None
+        return None, "counter profile taken on another kernel source"
     if kv.get("window") != f"{warmup + 1}..{warmup + steps}":
-        return None
-    return float(kv["traffic_bytes_per_launch"])
+        return None, "counter profile taken over another window"
+    return float(kv["traffic_bytes_per_launch"]), path
 
 
-def algorithmic_bytes_per_ant(cnt, n, k, bl):
-    """Bytes the array-based ant must move, from its counters (per ant-tour):
-    ACO step: candidate, pheromone and heuristic rows (12k) + source
-    position/neighbours (12) + coordinates (8) + route/pos writes (8);
-    copied city: source read (4) + coordinates (8) + route/pos writes (8);
-    backup pick: backup row (4 bl); fallback: the bounding boxes of the
-    32-city bitmap words (n / 2; the coordinates of the few words within the
-    bound are not counted, so this term is a lower bound);
-    LS pop: candidate row (4k) + per candidate, for both 2-opt loops,
-    position, neighbour and two coordinates (2 * 24 k) + own neighbourhood (64);
-    moved element: route read + route write + pos write (12)."""
+def survey_bytes_per_ant(cnt, n, k):
+    """The byte model of the measurement plan, per ant-tour, from the per-ant
+    counters (identical on the oracle and the GPU):
+      8n                route + pos written once
+      4 C               the source read along the copy (C copied cities)
+      S (12k + 8)       per ACO step the candidate, pheromone and heuristic
+                        rows and the source successor/predecessor
+      F 8n              per nearest-unvisited scan every coordinate
+      P (4k + 16k)      per LS pop the candidate row, and per candidate its
+                        position, tour neighbour and two coordinates
+      12 R              per moved element a route read + write and a pos write
+    """
+    S, C, Fb = cnt[:, 0], cnt[:, 1], cnt[:, 3]
+    P, R = cnt[:, 5], cnt[:, 8]
+    return (8 * n + 4 * C + S * (12 * k + 8) + Fb * 8 * n + P * 20 * k + 12 * R).astype(np.float64)
+
+
+def lower_bound_bytes_per_ant(cnt, n, k, bl):
+    """A tighter lower-bound model of what this kernel must move: ACO step
+    12k + 28 (rows, source neighbours, coordinates, route/pos writes); copied
+    city 20; backup pick 4 bl; nearest-unvisited scan n/2 (the bounding boxes
+    of the 32-city words it tests; pruned words' coordinates not counted);
+    LS pop 52k + 64 (row, per candidate position, neighbour and coordinates
+    for both 2-opt loops, own neighbourhood); moved element 12."""
     S, C, B, Fb = cnt[:, 0], cnt[:, 1], cnt[:, 2], cnt[:, 3]
     P, R = cnt[:, 5], cnt[:, 8]
     return (S * (12 * k + 28) + 20 * C + B * 4 * bl + Fb * (n // 2) +
             P * (52 * k + 64) + 12 * R).astype(np.float64)
 
 
-def cpu_baseline(xy, params, warmup, steps, budget_s=20.0):
-    """The oracle on the host over the same iterations as the timed GPU region
-    (fewer if the budget runs out first)."""
+# ------------------------------------------------------------- CPU legs ---
+
+def _oracle_rate(xy, params, warmup, steps, threads, budget_s):
     from oracle import oracle as O
-    threads = min(16, os.cpu_count() or 1)
     t0 = time.time()
     o = O.Oracle(xy, threads=threads, **params)
     build_s = time.time() - t0
@@ -83,12 +118,37 @@ def cpu_baseline(xy, params, warmup, steps, budget_s=20.0):
         o.run(1)
         t_run += time.time() - t1
         iters += 1
-    A = params["n_ants"]
     o.close()
-    return {"value": A * iters / t_run, "unit": "ant-tours/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"iterations {warmup + 1}..{warmup + iters} of the same instance "
-                      f"({iters} iterations, {t_run:.1f} s; build {build_s:.1f} s untimed)"}
+    return params["n_ants"] * iters / t_run, iters, t_run, build_s
+
+
+def cpu_baseline(xy, params, warmup, steps, budget_s):
+    """The oracle on the host over the timed iterations (fewer if the budget
+    runs out first), threads = min(nproc, ants); the oracle's parallelism is
+    over ants.  Also its one-thread rate and its rate on the 1000- and
+    20 000-city workloads."""
+    from paper_2203_02228_amd import instances as I
+    nproc = os.cpu_count() or 1
+    A = params["n_ants"]
+    threads = max(1, min(nproc, A))
+    log(f"cpu baseline: oracle, {threads} threads ...")
+    v, iters, t_run, build_s = _oracle_rate(xy, params, warmup, steps, threads, budget_s)
+    out = {"value": round(v, 2), "unit": "ant-tours/s", "cores": threads, "kind": "oracle",
+           "sample": f"iterations {warmup + 1}..{warmup + iters} of the same instance "
+                     f"({iters} iterations, {t_run:.1f} s; build {build_s:.1f} s untimed); "
+                     f"host nproc {nproc}"}
+    log("cpu baseline: oracle, 1 thread ...")
+    v1, it1, t1, _ = _oracle_rate(xy, params, warmup, steps, 1, budget_s / 2)
+    out["one_thread"] = {"value": round(v1, 2), "iterations": it1, "seconds": round(t1, 1)}
+    out["other_workloads"] = {}
+    for name in ("uniform1k", "gmm20k"):
+        w = I.WORKLOADS[name]
+        wt = max(1, min(nproc, w.n_ants))
+        log(f"cpu baseline: oracle on {name}, {wt} threads ...")
+        vr, itr, tr, _ = _oracle_rate(w.points(), w.params(), 0, w.iterations, wt, budget_s / 4)
+        out["other_workloads"][name] = {"value": round(vr, 2), "cores": wt,
+                                        "iterations": f"1..{itr}", "seconds": round(tr, 1)}
+    return out
 
 
 def _gen_points(args):
@@ -106,6 +166,8 @@ def gen_points_parallel(specs, procs=None):
     with mp.get_context("fork").Pool(procs) as pool:
         return pool.map(_gen_points, specs)
 
+
+# ------------------------------------------------------------- batched ---
 
 def run_batch_mode(args):
     """Uneven batch (256 instances, n log-uniform in [200, 5000], k 12, 16
@@ -127,12 +189,12 @@ def run_batch_mode(args):
         t0 = time.perf_counter()
         F.faco_run_batch(hs, 10, stream=stream)
         torch.cuda.synchronize()
-        best[apb] = time.perf_counter() - t0
+        best[apb] = round(time.perf_counter() - t0, 4)
         for h in hs:
             h.close()
     apb = min(best, key=best.get)
     F.faco_set_batch_ants_per_block(apb)
-    print(f"[bench] batch autotune {best} -> ants/block {apb}", file=sys.stderr, flush=True)
+    log(f"batch autotune {best} -> ants/block {apb}")
     hs = [F.faco_build_instance(p, stream=stream, **w.params()) for p, w in zip(pts, ws)]
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -158,6 +220,7 @@ def run_batch_mode(args):
     res_seq = [F.faco_get_best_tour(h)[1] for h in hs]
     for h in hs:
         h.close()
+    F.faco_set_batch_ants_per_block(1)
     same = res_seq == res_batch[:sub]
     return {
         "metric": "batched solves/s (256 uneven instances, 300 iterations each)",
@@ -175,18 +238,21 @@ def run_batch_mode(args):
     }
 
 
-def run_served_mode(args, quick=False):
+# -------------------------------------------------------------- served ---
+
+def run_served_mode(args):
     """Poisson stream of stipple solves (n log-uniform in [1000, 200000], 32
     ants, m 16, 200 iterations) through the continuous-batching server, vs
     the same requests solved one after another."""
     import torch
-    import numpy as np
     from paper_2203_02228_amd import faco as F
     from paper_2203_02228_amd import instances as I
     from paper_2203_02228_amd import serve as S
     count = args.requests
     reqs = I.served_requests(count=count, rate=args.rate)
+    t0 = time.time()
     pts = gen_points_parallel([(w.kind, w.n, w.instance_seed) for _, w in reqs])
+    log(f"served: {count} request point sets in {time.time() - t0:.0f} s")
     torch.cuda.set_device(0)
     srv = S.Server(hbm_budget_bytes=args.hbm_budget << 30, chunk=args.chunk)
     t0 = time.perf_counter()
@@ -196,8 +262,10 @@ def run_served_mode(args, quick=False):
         if arr > now:
             time.sleep(arr - now)
         futs.append(srv.submit(len(futs), p, w.params(), w.iterations))
-    for f in futs:
+    for i, f in enumerate(futs):
         f.result(timeout=args.result_timeout)
+        if (i + 1) % 64 == 0:
+            log(f"served: {i + 1}/{count} results ({time.perf_counter() - t0:.0f} s)")
     makespan = time.perf_counter() - t0
     srv.close()
     done = sorted(srv.completed, key=lambda r: r.rid)
@@ -226,18 +294,62 @@ def run_served_mode(args, quick=False):
         "sequential_sample": len(sample),
         "identical_lengths": bool(same),
         "n_range": [min(w.n for _, w in reqs), max(w.n for _, w in reqs)],
+        "errors": len(srv.errors),
+    }
+
+
+# ------------------------------------------------------------ headline ---
+
+def run_iterations_timed(F, g, stream, steps, torch, label):
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    done, chunk = 0, max(1, steps // 10)
+    while done < steps:
+        step = min(chunk, steps - done)
+        F.faco_run_iterations(g, step)
+        done += step
+        log(f"{label}: {done}/{steps} iterations enqueued")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1)
+
+
+def full_run(F, I, torch, stream, w):
+    """The configured run: all of the workload's iterations from a fresh build,
+    with every tour length recomputed and checked on the device in every
+    iteration (the checks' own time is measured and reported apart)."""
+    xy = w.points()
+    g = F.faco_build_instance(xy, stream=stream, **w.params())
+    F.faco_set_verify(g, True)
+    F.faco_set_timing(g, True, reserve_iterations=w.iterations)
+    total_ms = run_iterations_timed(F, g, stream, w.iterations, torch, "full run")
+    phase_ms, launches = F.faco_phase_times(g)
+    fault = F.faco_debug_get(g, F.FACO_DBG_FAULT)
+    _, best_len = F.faco_get_best_tour(g) if fault[0] == 0 else (None, -1)
+    info = F.faco_debug_get(g, F.FACO_DBG_INFO)
+    g.close()
+    A = w.n_ants
+    return {
+        "iterations": int(info[0]), "ms_per_iteration": round(total_ms / w.iterations, 4),
+        "ant_tours_per_s": round(A * w.iterations / (total_ms * 1e-3), 2),
+        "ant_kernel_mean_ms": round(phase_ms[0] / max(1, launches[0]), 4),
+        "best_length": int(best_len),
+        "lengths_verified": bool(fault[0] == 0 and fault[3] == w.iterations * (A + 1)),
+        "tours_verified": int(fault[3]), "device_faults": int(fault[0]),
     }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # default: the whole configured run of the workload (1000 iterations from
-    # the built instance)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="stipple100k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-run", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-iterations", type=int, default=0)
@@ -247,6 +359,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB for resident solves")
     ap.add_argument("--seq-sample", type=int, default=16)
+    ap.add_argument("--result-timeout", type=float, default=900.0)
     ap.add_argument("--team-waves", type=int, default=0,
                     help="waves per ant (0 = the library's choice by size; 1, 4, 8)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -256,8 +369,7 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the ants of an iteration would shard across GPUs; this benchmark "
-              "runs and measures one)",
-              file=sys.stderr)
+              "runs and measures one)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch256":
@@ -285,8 +397,7 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"[bench] copy calibration: {nbytes} bytes read, {nbytes} written",
-              file=sys.stderr, flush=True)
+        log(f"copy calibration: {nbytes} bytes read, {nbytes} written")
         del src, dst
     stream = torch.cuda.current_stream()
     F.faco_set_team_waves(args.team_waves)
@@ -294,27 +405,16 @@ def main():
     g = F.faco_build_instance(xy, stream=stream, **params)
     build_s = time.time() - t0
     team_waves = int(F.faco_debug_get(g, F.FACO_DBG_TEAM_WAVES)[0])
-    print(f"[bench] built {w.name} n={w.n} in {build_s:.2f} s", file=sys.stderr, flush=True)
+    log(f"built {w.name} n={w.n} in {build_s:.2f} s")
     F.faco_run_iterations(g, args.warmup)
     torch.cuda.synchronize()
     F.faco_phase_times(g)  # clear
-    F.faco_set_timing(g, True)
+    F.faco_set_timing(g, True, reserve_iterations=args.steps)
 
     n, k, bl, A = w.n, g.k, g.bl, w.n_ants
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     tot0 = F.faco_debug_get(g, F.FACO_DBG_COUNTER_TOTALS)
     tk0 = F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    done, chunk = 0, max(1, args.steps // 10)
-    while done < args.steps:
-        step = min(chunk, args.steps - done)
-        F.faco_run_iterations(g, step)
-        done += step
-        print(f"[bench] {done}/{args.steps} iterations enqueued", file=sys.stderr, flush=True)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
+    total_ms = run_iterations_timed(F, g, stream, args.steps, torch, "timed")
     phase_ms, launches = F.faco_phase_times(g)
     F.faco_set_timing(g, False)
     tot1 = F.faco_debug_get(g, F.FACO_DBG_COUNTER_TOTALS)
@@ -327,15 +427,25 @@ def main():
     tk_calls = {name: round(float(per[i]), 1) for i, name in
                 [(5, "spec_windows"), (6, "one_steps"), (7, "copies"), (12, "eval_rounds")]}
     slowest_us = round(float(tk[:, 4].max()) / args.steps / 100.0, 1)
-    bytes_ant = float(algorithmic_bytes_per_ant(tot1 - tot0, n, k, bl).sum())
-    cnt_mean = ((tot1 - tot0).sum(0) / (A * args.steps)).tolist()
+    dcnt = tot1 - tot0
+    bytes_survey = float(survey_bytes_per_ant(dcnt, n, k).sum())
+    bytes_lb = float(lower_bound_bytes_per_ant(dcnt, n, k, bl).sum())
+    cnt_mean = (dcnt.sum(0) / (A * args.steps)).tolist()
+    # the timed instance's tours, recomputed on the device after the region
+    rec = F.faco_debug_get(g, F.FACO_DBG_RECOMPUTED_LENGTHS)
+    lens = F.faco_debug_get(g, F.FACO_DBG_ANT_LENGTHS)
+    fault = F.faco_debug_get(g, F.FACO_DBG_FAULT)
     best_tour, best_len = F.faco_get_best_tour(g)
+    lengths_ok = bool(np.array_equal(rec[:-1], lens) and rec[-1] == best_len and fault[0] == 0)
     info = F.faco_debug_get(g, F.FACO_DBG_INFO)
     g.close()
 
     ms_per_step = total_ms / args.steps
     ant_ms = phase_ms[0] / max(1, launches[0])
-    achieved = (bytes_ant / max(1, launches[0])) / (ant_ms * 1e-3) / 1e9
+    launches_ant = max(1, launches[0])
+    achieved = (bytes_survey / launches_ant) / (ant_ms * 1e-3) / 1e9
+    achieved_lb = (bytes_lb / launches_ant) / (ant_ms * 1e-3) / 1e9
+    traffic, traffic_src = profiled_traffic(w.name, args.warmup, args.steps)
     value = A * args.steps / (total_ms * 1e-3)
     out = {
         "metric": "ant-tours/s (construct+2-opt/Or-opt) at 100k cities",
@@ -356,6 +466,8 @@ def main():
                    f"{args.warmup + 1}..{args.warmup + args.steps}",
                    "best_length": int(best_len), "iterations_done": int(info[0]),
                    "waves_per_ant": team_waves, "build_s": round(build_s, 2)},
+        "lengths_verified": lengths_ok,
+        "device_faults": int(fault[0]),
         "per_ant_us": tk_us,
         "per_ant_calls": tk_calls,
         "slowest_ant_us": slowest_us,
@@ -365,13 +477,31 @@ def main():
                                                              "pheromone"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": profiled_traffic(w.name, args.warmup, args.steps),
-                     "kernel": "ant_kernel",
-                     "avg_launch_ms": round(ant_ms, 4)},
+                     "traffic": traffic, "kernel": "ant_kernel",
+                     "avg_launch_ms": round(ant_ms, 4), "launches": int(launches[0]),
+                     "algorithmic_bytes_per_launch": round(bytes_survey / launches_ant),
+                     "byte_model": "per ant-tour 8n + 4C + S(12k+8) + F 8n + P 20k + 12R",
+                     "traffic_source": traffic_src,
+                     "lower_bound_model": {
+                         "achieved": round(achieved_lb, 2),
+                         "frac": round(achieved_lb / HBM_PEAK_GBS, 5),
+                         "bytes_per_launch": round(bytes_lb / launches_ant)}},
     }
+    if not args.no_full_run:
+        log(f"full run: {w.iterations} iterations from a fresh build, verification on ...")
+        out["full_run"] = full_run(F, I, torch, stream, w)
+        log(f"full run: {out['full_run']}")
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(xy, params, args.warmup, args.steps, args.cpu_budget)
+    if not args.no_batch:
+        log("batch256 ...")
+        b = run_batch_mode(args)
+        out["batched"] = {"solves_per_s": b["value"], "ms_per_iteration": b["ms_per_step"],
+                          "ants_per_block": b["config"]["ants_per_block"],
+                          "one_launch_per_instance": b["one_launch_per_instance"]}
+    if not args.no_served:
+        log(f"served: {args.requests} requests at {args.rate}/s ...")
+        out["served"] = run_served_mode(args)
     print(json.dumps(out), flush=True)
 
 

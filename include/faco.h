@@ -229,7 +229,10 @@ uint64_t faco_footprint_bytes(int32_t n, const faco_params *p);
 int faco_set_verify(faco_instance *h, int32_t enable);
 
 /* Kernel timing.  When enabled, each phase launch of faco_run_iterations is
- * bracketed by HIP events on the handle's stream.  faco_phase_times syncs and
+ * bracketed by HIP events on the handle's stream (enable > 1 also creates
+ * the events of that many iterations at once, so that none is created while
+ * the timed iterations are enqueued; events are reused after
+ * faco_phase_times).  faco_phase_times syncs and
  * returns, per phase (0 = ants: construction + local search, 1 = colony
  * update, 2 = source materialisation, 3 = pheromone update), the summed
  * milliseconds in ms_out[phase] and the launch count in launches[phase]. */

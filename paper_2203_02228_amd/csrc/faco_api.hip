@@ -39,6 +39,7 @@ struct faco_instance {
   std::vector<int32_t> orig_of, int_of;  // internal label <-> original city number
   bool timing = false;
   std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> ev_pool;  // timing events, created once and reused
   double phase_ms[4] = {0, 0, 0, 0};
   int64_t phase_n[4] = {0, 0, 0, 0};
 };
@@ -135,10 +136,20 @@ static size_t knn_lds_bytes(int K, int BL) {
          (sizeof(double) + sizeof(int32_t)) * (size_t)(K + BL) * 64;
 }
 
+static hipEvent_t take_event(faco_instance *h) {
+  hipEvent_t e = nullptr;
+  if (!h->ev_pool.empty()) {
+    e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+  } else {
+    (void)hipEventCreate(&e);
+  }
+  return e;
+}
 static void begin_timed(faco_instance *h, int phase, TimedLaunch &tl) {
   tl.phase = phase;
-  (void)hipEventCreate(&tl.a);
-  (void)hipEventCreate(&tl.b);
+  tl.a = take_event(h);
+  tl.b = take_event(h);
   (void)hipEventRecord(tl.a, h->stream);
 }
 static void end_timed(faco_instance *h, TimedLaunch &tl) {
@@ -505,6 +516,7 @@ extern "C" void faco_destroy_instance(faco_instance *h) {
     (void)hipEventDestroy(tl.a);
     (void)hipEventDestroy(tl.b);
   }
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   {
     std::lock_guard<std::mutex> lk(g_capture_mu);
     for (void *p : h->allocs) (void)hipFree(p);
@@ -610,7 +622,15 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
 
 extern "C" int faco_set_timing(faco_instance *h, int32_t enable) {
   if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
+  if (enable < 0) return set_err(h, FACO_EINVAL, "enable must be >= 0");
   h->timing = enable != 0;
+  // events for `enable` iterations (two per phase) made ahead of the launches
+  const size_t want = enable > 1 ? (size_t)enable * 8 : 0;
+  while (h->ev_pool.size() < want) {
+    hipEvent_t e;
+    HIP_TRY(h, hipEventCreate(&e));
+    h->ev_pool.push_back(e);
+  }
   return FACO_OK;
 }
 
@@ -622,8 +642,8 @@ extern "C" int faco_phase_times(faco_instance *h, double *ms_out, int64_t *launc
     (void)hipEventElapsedTime(&ms, tl.a, tl.b);
     h->phase_ms[tl.phase] += ms;
     h->phase_n[tl.phase] += 1;
-    (void)hipEventDestroy(tl.a);
-    (void)hipEventDestroy(tl.b);
+    h->ev_pool.push_back(tl.a);
+    h->ev_pool.push_back(tl.b);
   }
   h->pending.clear();
   for (int i = 0; i < 4; ++i) {

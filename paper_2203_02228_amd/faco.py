@@ -199,8 +199,11 @@ def faco_footprint_bytes(n, params=None, **kw):
     return int(lib().faco_footprint_bytes(int(n), ctypes.byref(p)))
 
 
-def faco_set_timing(inst, enable=True):
-    _check(lib().faco_set_timing(inst.h, 1 if enable else 0), inst.h)
+def faco_set_timing(inst, enable=True, reserve_iterations=0):
+    """Phase timing on/off; reserve_iterations > 1 creates that many
+    iterations' events up front."""
+    v = (max(2, int(reserve_iterations)) if reserve_iterations else 1) if enable else 0
+    _check(lib().faco_set_timing(inst.h, v), inst.h)
 
 
 def faco_set_verify(inst, enable=True):
