@@ -125,6 +125,25 @@ const char *faco_last_error(const faco_instance *h);
 int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
                    void *hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): faco_run_batch
+ * without allocation.  The same launches and results as faco_run_batch, but
+ * the instance and ant tables live in a fixed array of 256 KiB that each
+ * device holds until the process ends, no graph is captured and no event is
+ * created; each iteration is launched directly.
+ *   Limits: at most 256 instances and 16384 ants (all instances together)
+ *   per call, else FACO_EINVAL.  Every handle must have been built on
+ *   hip_stream (the call adds no cross-stream ordering) and on the current
+ *   device, else FACO_EINVAL.
+ *   Calls on one device share the array: calls that overlap on the device
+ *   (different streams, or different host threads without ordering) race and
+ *   must not be made; calls in order on one stream are safe.
+ * Returns after enqueue.  Errors: FACO_EINVAL, FACO_EDEVICE.
+ */
+int faco_run_batch_noalloc(faco_instance *const *hs, int32_t count, int32_t iterations,
+                           void *hip_stream);
+
 /* Ants (wavefronts) per workgroup in faco_run_batch launches with one wave
  * per ant: 1, 2 or 4, lowered when their LDS would not fit a CU (process-
  * wide; an execution-shape choice that never changes results).

@@ -36,6 +36,7 @@ struct faco_instance {
   std::string err;
   size_t lds_ant = 0;
   int tw = 1;  // waves per ant in the per-instance ant kernel
+  int device = 0;  // the device current at build
   std::vector<int32_t> orig_of, int_of;  // internal label <-> original city number
   bool timing = false;
   std::vector<TimedLaunch> pending;
@@ -310,6 +311,10 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   h->n = n;
   effective_sizes(n, p, &h->k, &h->bl);
   h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return set_err(nullptr, FACO_EDEVICE, "hipGetDevice failed");
+  }
   const size_t N = (size_t)n, A = (size_t)p->n_ants, K = (size_t)h->k, BL = (size_t)h->bl;
   const size_t NB = (N + 63) / 64 * 64;
 
@@ -679,16 +684,91 @@ extern "C" int faco_set_batch_ants_per_block(int32_t apb) {
   return FACO_OK;
 }
 
+// Argument checks shared by the batched entry points.
+static const char *check_batch_args(faco_instance *const *hs, int32_t count,
+                                    int32_t iterations) {
+  if (!hs || count < 0) return "bad handle array";
+  if (iterations < 0) return "iterations must be >= 0";
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i]) return "NULL handle in batch";
+    for (int32_t j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return "handles must be distinct";
+  }
+  return nullptr;
+}
+
+static int batch_ant_count(faco_instance *const *hs, int32_t count) {
+  int total = 0;
+  for (int32_t i = 0; i < count; ++i) total += hs[i]->p.n_ants;
+  return total;
+}
+
+// Launch shape of one batch.
+struct BatchShape {
+  int count = 0, total = 0, kmax = 2, maxn = 0, max_ants = 0, tw = 1, apb = 1;
+  bool any_verify = false;
+  size_t lds_words = 0, max_slots = 0, lds_bytes = 0;
+  AntBatchFn antk = nullptr;
+};
+
+// Fill the host tables (insts[count], amap[total ants]) and derive the
+// launch shape.  Caller holds g_batch_mu.
+static void batch_shape(faco_instance *const *hs, int32_t count, Inst *insts, int2 *amap,
+                        BatchShape &B) {
+  B.count = count;
+  int w = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    faco_instance *h = hs[i];
+    insts[i] = h->dv;
+    B.kmax = h->k > B.kmax ? h->k : B.kmax;
+    B.maxn = h->n > B.maxn ? h->n : B.maxn;
+    B.max_ants = h->p.n_ants > B.max_ants ? h->p.n_ants : B.max_ants;
+    B.any_verify = B.any_verify || h->dv.verify;
+    const size_t words = 3 * (size_t)((h->n + 31) / 32) + (size_t)h->dv.lcap;
+    B.lds_words = words > B.lds_words ? words : B.lds_words;
+    const size_t slots = (size_t)h->n * (size_t)h->k;
+    B.max_slots = slots > B.max_slots ? slots : B.max_slots;
+    for (int a = 0; a < h->p.n_ants; ++a) amap[w++] = make_int2(i, a);
+  }
+  B.total = w;
+  // waves per ant (as for a lone instance, from the largest tour and the
+  // ant count); with one wave per ant, ants per workgroup: the setting,
+  // lowered until their LDS fits a CU
+  B.tw = team_waves_for(B.maxn, B.total);
+  B.apb = B.tw > 1 ? 1 : g_batch_apb;
+  while (B.apb > 1 && sizeof(uint32_t) * B.lds_words * (size_t)B.apb > kLdsBytes) B.apb >>= 1;
+  B.lds_bytes =
+      sizeof(uint32_t) * ((size_t)faco_team_lds_words(B.tw) + B.lds_words * (size_t)B.apb);
+  B.antk = faco_ant_batch_kernel(B.kmax, B.tw);
+}
+
+// The launches of one batched iteration over the device tables.
+static void enqueue_batch_iteration(const BatchShape &B, const Inst *d_insts,
+                                    const int2 *d_amap, hipStream_t s) {
+  const unsigned nb_ant = (unsigned)((B.total + B.apb - 1) / B.apb);
+  const dim3 g_src((unsigned)((B.maxn + 255) / 256), (unsigned)B.count);
+  const dim3 g_tau((unsigned)((B.max_slots + 255) / 256), (unsigned)B.count);
+  hipLaunchKernelGGL(B.antk, dim3(nb_ant), dim3(64 * (B.tw > 1 ? B.tw : B.apb)), B.lds_bytes,
+                     s, d_insts, d_amap, B.total, B.apb, (int)B.lds_words);
+  if (B.any_verify) {
+    hipLaunchKernelGGL(faco::verify_batch_kernel,
+                       dim3(faco::verify_chunks(B.maxn), (unsigned)B.max_ants + 1,
+                            (unsigned)B.count),
+                       dim3(faco::kVerifyBlock), 0, s, d_insts);
+    hipLaunchKernelGGL(faco::verify_finish_batch_kernel, dim3((unsigned)B.count),
+                       dim3(faco::kVerifyBlock), 0, s, d_insts);
+  }
+  hipLaunchKernelGGL(faco::colony_batch_kernel, dim3((unsigned)B.count), dim3(64), 0, s,
+                     d_insts);
+  hipLaunchKernelGGL(faco::source_batch_kernel, g_src, dim3(256), 0, s, d_insts);
+  hipLaunchKernelGGL(faco::pheromone_batch_kernel, g_tau, dim3(256), 0, s, d_insts);
+}
+
 extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
                               void *hip_stream) {
-  if (!hs || count < 0) return set_err(nullptr, FACO_EINVAL, "bad handle array");
-  if (iterations < 0) return set_err(nullptr, FACO_EINVAL, "iterations must be >= 0");
+  if (const char *m = check_batch_args(hs, count, iterations))
+    return set_err(nullptr, FACO_EINVAL, m);
   if (count == 0 || iterations == 0) return FACO_OK;
-  for (int32_t i = 0; i < count; ++i) {
-    if (!hs[i]) return set_err(nullptr, FACO_EINVAL, "NULL handle in batch");
-    for (int32_t j = 0; j < i; ++j)
-      if (hs[j] == hs[i]) return set_err(nullptr, FACO_EINVAL, "handles must be distinct");
-  }
   std::lock_guard<std::mutex> lk(g_batch_mu);
   hipStream_t st = (hipStream_t)hip_stream;
   BatchWs &g_ws = g_ws_map[st];
@@ -697,33 +777,11 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
   if ((e = (expr)) != hipSuccess)                                                     \
     return set_err(nullptr, FACO_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e));
   // host tables
-  std::vector<Inst> insts(count);
-  std::vector<int2> amap;
-  int kmax = 2, maxn = 0, max_ants = 0;
-  bool any_verify = false;
-  size_t lds_words = 0, max_slots = 0;
-  for (int32_t i = 0; i < count; ++i) {
-    faco_instance *h = hs[i];
-    insts[i] = h->dv;
-    kmax = h->k > kmax ? h->k : kmax;
-    maxn = h->n > maxn ? h->n : maxn;
-    max_ants = h->p.n_ants > max_ants ? h->p.n_ants : max_ants;
-    any_verify = any_verify || h->dv.verify;
-    const size_t words = 3 * (size_t)((h->n + 31) / 32) + (size_t)h->dv.lcap;
-    lds_words = words > lds_words ? words : lds_words;
-    const size_t slots = (size_t)h->n * (size_t)h->k;
-    max_slots = slots > max_slots ? slots : max_slots;
-    for (int a = 0; a < h->p.n_ants; ++a) amap.push_back(make_int2(i, a));
-  }
-  const int total = (int)amap.size();
-  // waves per ant (as for a lone instance, from the largest tour and the
-  // ant count); with one wave per ant, ants per workgroup: the setting,
-  // lowered until their LDS fits a CU
-  const int tw = team_waves_for(maxn, total);
-  int apb = tw > 1 ? 1 : g_batch_apb;
-  while (apb > 1 && sizeof(uint32_t) * lds_words * (size_t)apb > kLdsBytes) apb >>= 1;
-  const size_t lds_bytes =
-      sizeof(uint32_t) * ((size_t)faco_team_lds_words(tw) + lds_words * (size_t)apb);
+  std::vector<Inst> insts((size_t)count);
+  std::vector<int2> amap((size_t)batch_ant_count(hs, count));
+  BatchShape B;
+  batch_shape(hs, count, insts.data(), amap.data(), B);
+  const int total = B.total;
   // the tables are shared: the previous batch must be done with them
   if (!g_ws.last_done) BT(hipEventCreateWithFlags(&g_ws.last_done, hipEventDisableTiming));
   const bool grow = g_ws.cap_insts < (size_t)count || g_ws.cap_amap < (size_t)total;
@@ -757,32 +815,10 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
                     hipMemcpyHostToDevice, st));
   BT(hipMemcpyAsync(g_ws.amap, amap.data(), sizeof(int2) * (size_t)total,
                     hipMemcpyHostToDevice, st));
-  AntBatchFn antk = faco_ant_batch_kernel(kmax, tw);
-  BT(hipFuncSetAttribute((const void *)antk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                         (int)lds_bytes));
-  const unsigned nb_ant = (unsigned)((total + apb - 1) / apb);
-  const dim3 g_src((unsigned)((maxn + 255) / 256), (unsigned)count);
-  const dim3 g_tau((unsigned)((max_slots + 255) / 256), (unsigned)count);
-  auto enqueue = [&](hipStream_t s) {
-    hipLaunchKernelGGL(antk, dim3(nb_ant), dim3(64 * (tw > 1 ? tw : apb)), lds_bytes, s,
-                       g_ws.insts, g_ws.amap, total, apb, (int)lds_words);
-    if (any_verify) {
-      hipLaunchKernelGGL(faco::verify_batch_kernel,
-                         dim3(faco::verify_chunks(maxn), (unsigned)max_ants + 1,
-                              (unsigned)count),
-                         dim3(faco::kVerifyBlock), 0, s, (const Inst *)g_ws.insts);
-      hipLaunchKernelGGL(faco::verify_finish_batch_kernel, dim3((unsigned)count),
-                         dim3(faco::kVerifyBlock), 0, s, (const Inst *)g_ws.insts);
-    }
-    hipLaunchKernelGGL(faco::colony_batch_kernel, dim3((unsigned)count), dim3(64), 0, s,
-                       (const Inst *)g_ws.insts);
-    hipLaunchKernelGGL(faco::source_batch_kernel, g_src, dim3(256), 0, s,
-                       (const Inst *)g_ws.insts);
-    hipLaunchKernelGGL(faco::pheromone_batch_kernel, g_tau, dim3(256), 0, s,
-                       (const Inst *)g_ws.insts);
-  };
+  BT(hipFuncSetAttribute((const void *)B.antk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                         (int)B.lds_bytes));
   if (iterations == 1) {
-    enqueue(st);
+    enqueue_batch_iteration(B, g_ws.insts, g_ws.amap, st);
     BT(hipGetLastError());
   } else {
     // one iteration captured as a graph, replayed
@@ -793,7 +829,7 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
     {
       std::lock_guard<std::mutex> lk(g_capture_mu);
       BT(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-      enqueue(cap);
+      enqueue_batch_iteration(B, g_ws.insts, g_ws.amap, cap);
       BT(hipStreamEndCapture(cap, &graph));
     }
     BT(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -806,6 +842,94 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
   BT(hipEventRecord(g_ws.last_done, st));
   for (int32_t i = 0; i < count; ++i)
     if (hs[i]->stream != st) BT(hipStreamWaitEvent(hs[i]->stream, g_ws.last_done, 0));
+#undef BT
+  return FACO_OK;
+}
+
+// ------------------------------------------------------------------------
+// faco_run_batch_noalloc: the launches of faco_run_batch with the instance
+// and ant tables in a fixed device array instead of an allocated workspace,
+// and without graph capture or events.
+
+constexpr int kNoAllocMaxInstances = 256;
+constexpr int kNoAllocMaxAnts = 16384;
+constexpr size_t kScratchInstBytes = (size_t)kNoAllocMaxInstances * sizeof(Inst);
+constexpr size_t kScratchBytes = 256 * 1024;
+static_assert(kScratchInstBytes % 256 == 0, "ant table must stay aligned");
+static_assert(kScratchInstBytes + (size_t)kNoAllocMaxAnts * sizeof(int2) <= kScratchBytes,
+              "tables exceed the fixed array");
+
+// Each device holds its own copy until the process ends.  In host code the
+// name is a stand-in for the symbol only: the device address of each copy
+// comes from hipGetSymbolAddress and is the only thing passed to copies and
+// kernels.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_dev[kMaxDevices];  // looked up once per device
+
+// Device address of `scratch` on device dev (which must be current).
+static int scratch_address(int dev, unsigned char **out) {
+  if (dev < 0 || dev >= kMaxDevices) return set_err(nullptr, FACO_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_err(nullptr, FACO_EDEVICE,
+                     std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (unsigned char *)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return FACO_OK;
+}
+
+// host staging of the tables (guarded by g_batch_mu)
+static Inst g_na_insts[kNoAllocMaxInstances];
+static int2 g_na_amap[kNoAllocMaxAnts];
+
+extern "C" int faco_run_batch_noalloc(faco_instance *const *hs, int32_t count,
+                                      int32_t iterations, void *hip_stream) {
+  if (const char *m = check_batch_args(hs, count, iterations))
+    return set_err(nullptr, FACO_EINVAL, m);
+  if (count == 0 || iterations == 0) return FACO_OK;
+  if (count > kNoAllocMaxInstances)
+    return set_err(nullptr, FACO_EINVAL,
+                   "faco_run_batch_noalloc: at most 256 instances per call");
+  if (batch_ant_count(hs, count) > kNoAllocMaxAnts)
+    return set_err(nullptr, FACO_EINVAL,
+                   "faco_run_batch_noalloc: at most 16384 ants per call (all instances)");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0;
+  hipError_t e;
+#define BT(expr)                                                                      \
+  if ((e = (expr)) != hipSuccess)                                                     \
+    return set_err(nullptr, FACO_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e));
+  BT(hipGetDevice(&dev));
+  for (int32_t i = 0; i < count; ++i) {
+    if (hs[i]->stream != st)
+      return set_err(nullptr, FACO_EINVAL,
+                     "faco_run_batch_noalloc: every handle must run on hip_stream");
+    if (hs[i]->device != dev)
+      return set_err(nullptr, FACO_EINVAL,
+                     "faco_run_batch_noalloc: every handle must live on the current device");
+  }
+  unsigned char *base = nullptr;
+  if (int rc = scratch_address(dev, &base)) return rc;
+  Inst *d_insts = reinterpret_cast<Inst *>(base);
+  int2 *d_amap = reinterpret_cast<int2 *>(base + kScratchInstBytes);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchShape B;
+  batch_shape(hs, count, g_na_insts, g_na_amap, B);
+  BT(hipMemcpyAsync(d_insts, g_na_insts, sizeof(Inst) * (size_t)count, hipMemcpyHostToDevice,
+                    st));
+  BT(hipMemcpyAsync(d_amap, g_na_amap, sizeof(int2) * (size_t)B.total, hipMemcpyHostToDevice,
+                    st));
+  BT(hipFuncSetAttribute((const void *)B.antk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                         (int)B.lds_bytes));
+  for (int32_t it = 0; it < iterations; ++it) enqueue_batch_iteration(B, d_insts, d_amap, st);
+  BT(hipGetLastError());
 #undef BT
   return FACO_OK;
 }

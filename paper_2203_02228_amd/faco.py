@@ -30,7 +30,7 @@ EXPORTED = ["faco_build_instance", "faco_run_iterations", "faco_get_best_tour",
             "faco_destroy_instance", "faco_last_error", "faco_run_batch",
             "faco_debug_get", "faco_footprint_bytes", "faco_set_timing",
             "faco_phase_times", "faco_set_batch_ants_per_block", "faco_set_team_waves",
-            "faco_set_queue_lds_capacity", "faco_set_verify"]
+            "faco_set_queue_lds_capacity", "faco_set_verify", "faco_run_batch_noalloc"]
 
 
 class faco_params(ctypes.Structure):
@@ -80,6 +80,8 @@ def lib():
         L.faco_last_error.argtypes = [vp]
         L.faco_run_batch.restype = ctypes.c_int
         L.faco_run_batch.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int32, vp]
+        L.faco_run_batch_noalloc.restype = ctypes.c_int
+        L.faco_run_batch_noalloc.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int32, vp]
         L.faco_debug_get.restype = ctypes.c_int
         L.faco_debug_get.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_size_t]
         L.faco_footprint_bytes.restype = ctypes.c_uint64
@@ -176,6 +178,14 @@ def faco_destroy_instance(inst):
 def faco_run_batch(insts, iterations, stream=None):
     arr = (ctypes.c_void_p * len(insts))(*[i.h for i in insts])
     rc = lib().faco_run_batch(arr, len(insts), int(iterations), _stream_handle(stream))
+    _check(rc)
+
+
+def faco_run_batch_noalloc(insts, iterations, stream=None):
+    """faco_run_batch without device allocation (fixed tables; every handle
+    built on `stream`)."""
+    arr = (ctypes.c_void_p * len(insts))(*[i.h for i in insts])
+    rc = lib().faco_run_batch_noalloc(arr, len(insts), int(iterations), _stream_handle(stream))
     _check(rc)
 
 
