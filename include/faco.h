@@ -75,7 +75,8 @@ typedef struct faco_instance faco_instance;
  * from city 0 improved by the local search over all cities), the trail limits,
  * tau = tau_max everywhere, source = initial solution.
  *   xy         host pointer, n rows of (x, y) int32, row-major; each
- *              coordinate in [0, 2^23).  Copied; the caller keeps ownership.
+ *              coordinate in [0, 2^26) (squared lengths below 2^53, exact
+ *              in binary64).  Copied; the caller keeps ownership.
  *   n          number of cities, 4 .. 262144 (2^18).
  *   p          parameters, copied.
  *   hip_stream hipStream_t to run on (NULL = the default stream).  The handle

@@ -28,7 +28,8 @@
 /* ------------------------------------------------------------------------ */
 /* Distances.  The paper's problem statement (Sec. 2.1) only asks for
  * positive symmetric costs; its instances are TSPLIB/TSP-Art instances with
- * integer lengths.  reading: cost = TSPLIB EUC_2D, nint(sqrt(dx^2+dy^2)). */
+ * integer lengths.  reading: cost = TSPLIB EUC_2D, nint(sqrt(dx^2+dy^2)),
+ * coordinates in [0, 2^26) so that dx^2 + dy^2 < 2^53. */
 
 static inline int64_t sqd(const int32_t *xy, int32_t i, int32_t j) {
   int64_t dx = (int64_t)xy[2 * i] - (int64_t)xy[2 * j];
@@ -36,9 +37,22 @@ static inline int64_t sqd(const int32_t *xy, int32_t i, int32_t j) {
   return dx * dx + dy * dy;
 }
 
-static inline int32_t dist(const int32_t *xy, int32_t i, int32_t j) {
-  return (int32_t)floor(sqrt((double)sqd(xy, i, j)) + 0.5);
+/* nint(sqrt(d2)) for an integer d2 >= 0, by integer arithmetic: r = floor of
+ * the square root (r^2 <= d2 < (r+1)^2, found from a floating-point start and
+ * settled with exact int64 products), then r + 1 when d2 > r^2 + r, i.e. when
+ * sqrt(d2) > r + 1/2 (sqrt(d2) is never a half-integer). */
+static inline int32_t nint_sqrt(int64_t d2) {
+  int64_t r = (int64_t)sqrt((double)d2);
+  while (r > 0 && r * r > d2) --r;
+  while ((r + 1) * (r + 1) <= d2) ++r;
+  return (int32_t)(r + (d2 > r * r + r ? 1 : 0));
 }
+
+static inline int32_t dist(const int32_t *xy, int32_t i, int32_t j) {
+  return nint_sqrt(sqd(xy, i, j));
+}
+
+int32_t orc_nint_sqrt(int64_t d2) { return nint_sqrt(d2); }
 
 int32_t orc_dist(const int32_t *xy, int32_t i, int32_t j) {
   return dist(xy, i, j);
@@ -745,7 +759,7 @@ orc_instance *orc_build(const int32_t *xy, int32_t n, const orc_params *p,
       (p->min_new_edges_max > 0 && p->min_new_edges_max < p->min_new_edges))
     return NULL;
   for (int32_t i = 0; i < 2 * n; ++i)
-    if (xy[i] < 0 || xy[i] >= (1 << 23)) return NULL;
+    if (xy[i] < 0 || xy[i] >= (1 << 26)) return NULL;
   orc_instance *h = (orc_instance *)calloc(1, sizeof(orc_instance));
   h->n = n;
   h->p = *p;

@@ -124,6 +124,7 @@ int64_t orc_best_move_gain(const orc_instance *h, const int32_t *route,
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2],
                        uint64_t out[4]);
 int32_t orc_dist(const int32_t *xy, int32_t i, int32_t j);
+int32_t orc_nint_sqrt(int64_t d2); /* nint(sqrt(d2)), d2 >= 0 */
 int64_t orc_tour_length(const int32_t *xy, int32_t n, const int32_t *route);
 
 #ifdef __cplusplus

@@ -75,6 +75,8 @@ def lib():
         L.orc_best_move_gain.restype = ctypes.c_int64
         L.orc_best_move_gain.argtypes = [vp, i32p, ctypes.c_int32, ctypes.c_uint32]
         L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.orc_nint_sqrt.restype = ctypes.c_int32
+        L.orc_nint_sqrt.argtypes = [ctypes.c_int64]
         L.orc_dist.restype = ctypes.c_int32
         L.orc_dist.argtypes = [i32p, ctypes.c_int32, ctypes.c_int32]
         L.orc_tour_length.restype = ctypes.c_int64
@@ -99,6 +101,10 @@ def philox4x64_10(ctr, key):
 def dist(xy, i, j):
     xy = np.ascontiguousarray(xy, dtype=np.int32)
     return int(lib().orc_dist(_p(xy, ctypes.c_int32), int(i), int(j)))
+
+
+def nint_sqrt(d2):
+    return int(lib().orc_nint_sqrt(int(d2)))
 
 
 def tour_length(xy, route):

@@ -144,8 +144,8 @@ FACO_DEV void bit_clear(uint32_t *bm, int x) {
 }
 
 // ---------------------------------------------------------------- cost ---
-// TSPLIB EUC_2D: nint(sqrt(dx^2 + dy^2)).  With |dx|,|dy| < 2^23 the squared
-// length is an exact integer below 2^47.
+// TSPLIB EUC_2D: nint(sqrt(dx^2 + dy^2)).  With |dx|,|dy| < 2^26 the squared
+// length is an exact integer below 2^53 in binary64.
 
 FACO_DEV double sqd(int2 a, int2 b) {
   double dx = (double)(a.x - b.x);
@@ -157,17 +157,22 @@ FACO_DEV uint64_t sqd_u64(int2 a, int2 b) {
   const uint32_t ax = (uint32_t)(dx < 0 ? -dx : dx), ay = (uint32_t)(dy < 0 ? -dy : dy);
   return (uint64_t)ax * ax + (uint64_t)ay * ay;
 }
+// nint(sqrt(d2)) for an integer d2 < 2^53 (held exactly).  It is the unique
+// C >= 0 with C^2 - C < d2 <= C^2 + C (d2 = 0: C = 0), because sqrt(d2) is
+// never a half-integer.  The hardware square root estimates sqrt(d2) to far
+// better than +-0.5, so its nearest integer r is C or a neighbour.  The fused
+// multiply-add gives e = r^2 - d2 exactly (a small integer; the product is
+// not rounded), and C = r unless e < -r (C = r + 1) or e >= r > 0 (C = r - 1).
+FACO_DEV int nint_sqrt(double d2) {
+  const double r = __builtin_rint(__builtin_amdgcn_sqrt(d2));
+  const double e = __builtin_fma(r, r, -d2);
+  return (int)r + (e < -r ? 1 : 0) - (e >= r && r > 0.0 ? 1 : 0);
+}
+
 FACO_DEV int cost(int2 a, int2 b) {
-  // d2 = dx^2 + dy^2 < 2^47 is exact in binary64.  nint(sqrt(d2)) is the
-  // unique C >= 0 with C^2 - C < d2 <= C^2 + C (d2 = 0: C = 0), because
-  // sqrt(d2) is never a half-integer.  The hardware square root estimates
-  // it to far better than +-0.5, so its rounding r is C or a neighbour; the
-  // two tests below, exact in binary64 (r^2 + r < 2^48), settle which.
+  // dy^2 < 2^52 and dx^2 + dy^2 < 2^53 are exact; the fused form rounds once
   const double dx = (double)(a.x - b.x), dy = (double)(a.y - b.y);
-  const double d2 = dx * dx + dy * dy;
-  const int r = (int)(__builtin_amdgcn_sqrt(d2) + 0.5);
-  const double rd = (double)r, rr = rd * rd;
-  return r + (d2 > rr + rd ? 1 : 0) - (r > 0 && d2 <= rr - rd ? 1 : 0);
+  return nint_sqrt(__builtin_fma(dx, dx, dy * dy));
 }
 
 // ----------------------------------------------------------- Philox4x64 ---

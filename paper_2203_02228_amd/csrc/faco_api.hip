@@ -303,8 +303,8 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   if (!xy) return set_err(nullptr, FACO_EINVAL, "xy is NULL");
   if (const char *m = validate(p, n)) return set_err(nullptr, FACO_EINVAL, m);
   for (int64_t i = 0; i < 2 * (int64_t)n; ++i)
-    if (xy[i] < 0 || xy[i] >= (1 << 23))
-      return set_err(nullptr, FACO_EINVAL, "coordinates must be in [0, 2^23)");
+    if (xy[i] < 0 || xy[i] >= (1 << 26))
+      return set_err(nullptr, FACO_EINVAL, "coordinates must be in [0, 2^26)");
 
   faco_instance *h = new faco_instance();
   h->p = *p;

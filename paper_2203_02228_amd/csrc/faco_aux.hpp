@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, const int32_t *
   for (int s = 0; s < K; ++s) {
     const double d2 = kd[s * 64 + tid];
     cl[(size_t)i * K + s] = int_of[ko[s * 64 + tid]];
-    const int d = (int)floor(sqrt(d2) + 0.5);
+    const int d = nint_sqrt(d2);
     cl_d[(size_t)i * K + s] = d;
     eta[(size_t)i * K + s] = (float)(1.0 / (double)d);
   }

@@ -137,11 +137,11 @@ def test_build_errors():
 
 
 def test_full_coordinate_range():
-    """Coordinates up to 2^23 - 1 (squared lengths up to 2^47): the cost
+    """Coordinates up to 2^26 - 1 (squared lengths up to 2^53): the cost
     function's extreme range, including near-collinear and far pairs."""
     rng = np.random.default_rng(77)
-    pts = rng.integers(0, (1 << 23), size=(1500, 2))
-    pts[:20, 0] = (1 << 23) - 1 - np.arange(20)       # a column at the far edge
+    pts = rng.integers(0, (1 << 26), size=(1500, 2))
+    pts[:20, 0] = (1 << 26) - 1 - np.arange(20)       # a column at the far edge
     pts[20:40] = np.stack([np.arange(20) * 3, np.zeros(20, np.int64)], 1)  # tight row
     xy = np.unique(pts, axis=0).astype(np.int32)
     xy = xy[rng.permutation(len(xy))]

@@ -58,7 +58,7 @@ def _exact_nint_sqrt(d2):
 
 def test_euc2d_exact_over_coordinate_range():
     rng = np.random.default_rng(1)
-    hi = (1 << 23) - 1
+    hi = (1 << 26) - 1
     pts = rng.integers(0, hi + 1, size=(4000, 2)).astype(np.int32)
     # corners and near-half-integer distances
     extra = np.array([[0, 0], [hi, hi], [hi, 0], [0, hi], [3, 4], [0, 1]], np.int32)
@@ -69,7 +69,7 @@ def test_euc2d_exact_over_coordinate_range():
         dy = int(xy[i, 1]) - int(xy[i + 1, 1])
         assert O.dist(xy, i, i + 1) == _exact_nint_sqrt(dx * dx + dy * dy)
     # r^2 + r and r^2 + r + 1 straddle the rounding boundary
-    for r in [1, 2, 1000, 999_999, 1_414_213, 8_388_000]:
+    for r in [1, 2, 1000, 999_999, 1_414_213, 8_388_000, 67_108_000, 94_900_000]:
         for d2 in (r * r + r, r * r + r + 1, r * r):
             a = int(math.isqrt(d2 // 2))
             b = d2 - a * a
@@ -77,9 +77,24 @@ def test_euc2d_exact_over_coordinate_range():
             if sb * sb != b:
                 continue
             xy2 = np.array([[0, 0], [a, sb]], np.int32)
-            if a >= (1 << 23) or sb >= (1 << 23):
+            if a >= (1 << 26) or sb >= (1 << 26):
                 continue
             assert O.dist(xy2, 0, 1) == _exact_nint_sqrt(d2)
+
+
+def test_nint_sqrt_at_every_rounding_boundary():
+    """nint(sqrt(d2)) flips exactly between r^2 + r and r^2 + r + 1, for r
+    up to the largest squared length of the coordinate range (2 * 2^52)."""
+    rng = np.random.default_rng(3)
+    rs = [1, 2, 3, 10, 46340, 46341, 2**23, 2**26 - 1, 2**26, 94_906_265]
+    rs += [int(x) for x in rng.integers(1, 94_906_265, size=400)]
+    for r in rs:
+        for d2 in (r * r - r, r * r - r + 1, r * r, r * r + r, r * r + r + 1):
+            if d2 >= 2**53:
+                continue
+            assert O.nint_sqrt(d2) == _exact_nint_sqrt(d2), d2
+    for d2 in [int(x) for x in rng.integers(0, 2**53, size=2000, dtype=np.int64)]:
+        assert O.nint_sqrt(d2) == _exact_nint_sqrt(d2), d2
 
 
 # ----------------------------------------------------------------- lists ---
@@ -140,7 +155,7 @@ def test_invalid_inputs_rejected():
     with pytest.raises(ValueError):
         O.Oracle(xy, rho=1.0)
     big = xy.copy()
-    big[0, 0] = 1 << 23
+    big[0, 0] = 1 << 26
     with pytest.raises(ValueError):
         O.Oracle(big)
 
