@@ -409,10 +409,11 @@ static inline int32_t t_pred(const tour_t *T, int32_t x) {
 }
 
 typedef struct {
-  int kind; /* 0 none, 1 2-opt, 2 or-opt */
+  int kind; /* 0 none, 1 2-opt, 2 or-opt, 3 3-opt */
   int64_t gain;
   int32_t w, x, y, z;                 /* 2-opt: remove (w,x),(y,z) */
   int32_t f, l, p, q, a, o, b, e, L; /* or-opt */
+  int32_t t[6], dir;                 /* 3-opt: t1..t6, orientation */
 } move_t;
 
 static void eval_2opt(const orc_instance *h, const tour_t *T, int32_t a,
@@ -513,12 +514,73 @@ static void eval_oropt(const orc_instance *h, const tour_t *T, int32_t a,
   }
 }
 
+/* 3-opt.  The paper improves its initial solution with 2-opt and 3-opt
+ * following Bentley (Sec. 4.3, after Alg. 2) without defining the move set.
+ * reading: the pure 3-opt reconnection (no segment reversed), searched from
+ * t1 = a over the candidate lists with positive partial gains (the rule
+ * that keeps neighbour-list searches complete), in both orientations.
+ * Orientation succ: t2 = succ(t1); t3 in cl(t2), t3 != t1, with
+ * g1 = d(t1,t2) - d(t2,t3) > 0; t4 = succ(t3), t4 != t1; t5 in cl(t4) with
+ * g2 = g1 + d(t3,t4) - d(t4,t5) > 0 and t5 on the path t2..t3 before t3;
+ * t6 = succ(t5); gain = g2 + d(t5,t6) - d(t6,t1).  The tour
+ * t1 [t2..t5] [t6..t3] t4 becomes t1 [t6..t3] [t2..t5] t4: the two blocks
+ * exchange places and keep their orientation.  Orientation pred: the same
+ * with pred for succ.  Best improvement, strict >; order: succ then pred,
+ * t3 in list order, t5 in list order. */
+static int32_t t_step(const tour_t *T, int32_t x, int dir) {
+  return dir == 0 ? t_succ(T, x) : t_pred(T, x);
+}
+/* positions from `from` to x along the orientation */
+static int32_t t_offset(const tour_t *T, int32_t from, int32_t x, int dir) {
+  const int32_t n = T->n;
+  return dir == 0 ? (T->pos[x] - T->pos[from] + n) % n : (T->pos[from] - T->pos[x] + n) % n;
+}
+
+static void eval_3opt(const orc_instance *h, const tour_t *T, int32_t a,
+                      move_t *mv) {
+  for (int dir = 0; dir < 2; ++dir) {
+    const int32_t t1 = a, t2 = t_step(T, t1, dir);
+    const int64_t d12 = dist(h->xy, t1, t2);
+    const int32_t *nn2 = h->cl + (size_t)t2 * h->k;
+    for (int32_t s = 0; s < h->k; ++s) {
+      const int32_t t3 = nn2[s];
+      const int64_t g1 = d12 - dist(h->xy, t2, t3);
+      if (g1 <= 0 || t3 == t1) continue;
+      const int32_t t4 = t_step(T, t3, dir);
+      if (t4 == t1) continue;
+      const int32_t off3 = t_offset(T, t2, t3, dir);
+      const int64_t d34 = dist(h->xy, t3, t4);
+      const int32_t *nn4 = h->cl + (size_t)t4 * h->k;
+      for (int32_t r = 0; r < h->k; ++r) {
+        const int32_t t5 = nn4[r];
+        const int64_t g2 = g1 + d34 - dist(h->xy, t4, t5);
+        if (g2 <= 0) continue;
+        if (t_offset(T, t2, t5, dir) >= off3) continue;
+        const int32_t t6 = t_step(T, t5, dir);
+        const int64_t g = g2 + dist(h->xy, t5, t6) - dist(h->xy, t6, t1);
+        if (g > mv->gain) {
+          mv->gain = g;
+          mv->kind = 3;
+          mv->dir = dir;
+          mv->t[0] = t1;
+          mv->t[1] = t2;
+          mv->t[2] = t3;
+          mv->t[3] = t4;
+          mv->t[4] = t5;
+          mv->t[5] = t6;
+        }
+      }
+    }
+  }
+}
+
 static void best_move(const orc_instance *h, const tour_t *T, int32_t a,
                       uint32_t flags, move_t *mv) {
   mv->kind = 0;
   mv->gain = 0;
   if (flags & ORC_LS_2OPT) eval_2opt(h, T, a, mv);
   if (mv->kind == 0 && (flags & ORC_LS_OROPT)) eval_oropt(h, T, a, mv);
+  if (mv->kind == 0 && (flags & ORC_LS_INIT_3OPT)) eval_3opt(h, T, a, mv);
 }
 
 /* reverse the cyclic array range of length L starting at position s */
@@ -600,6 +662,37 @@ static int64_t apply_oropt(tour_t *T, const move_t *mv, int32_t *tmp) {
   return D2 + L;
 }
 
+/* 3-opt realisation: in array order the range covered by the two blocks
+ * ([t2..t5][t6..t3] for orientation succ, [t3..t6][t5..t2] for pred) is
+ * rewritten with the second block first; both keep their orientation and
+ * nothing outside the range moves. */
+static int64_t apply_3opt(tour_t *T, const move_t *mv, int32_t *tmp) {
+  const int32_t n = T->n;
+  const int32_t *t = mv->t;
+  int32_t s, L1, L2;
+  if (mv->dir == 0) {
+    s = T->pos[t[1]];
+    L1 = (T->pos[t[4]] - s + n) % n + 1;
+    L2 = (T->pos[t[2]] - T->pos[t[5]] + n) % n + 1;
+  } else {
+    s = T->pos[t[2]];
+    L1 = (T->pos[t[5]] - s + n) % n + 1;
+    L2 = (T->pos[t[1]] - T->pos[t[4]] + n) % n + 1;
+  }
+  for (int32_t i = 0; i < L1 + L2; ++i) tmp[i] = T->route[(s + i) % n];
+  for (int32_t i = 0; i < L2; ++i) {
+    int32_t ps = (s + i) % n;
+    T->route[ps] = tmp[L1 + i];
+    T->pos[tmp[L1 + i]] = ps;
+  }
+  for (int32_t i = 0; i < L1; ++i) {
+    int32_t ps = (s + L2 + i) % n;
+    T->route[ps] = tmp[i];
+    T->pos[tmp[i]] = ps;
+  }
+  return L1 + L2;
+}
+
 typedef struct {
   int32_t *ring, *tmp, *pos;
   uint8_t *inq, *touched, *visited;
@@ -675,6 +768,13 @@ static int64_t local_search(const orc_instance *h, int32_t *route,
         PUSH(mv.l);
         if (cnt) {
           cnt[ORC_CNT_MOVES_OROPT]++;
+          cnt[ORC_CNT_MOVED_ELEMS] += r;
+        }
+      } else if (mv.kind == 3) {
+        int64_t r = apply_3opt(&T, &mv, S->tmp);
+        for (int i = 0; i < 6; ++i) PUSH(mv.t[i]);
+        if (cnt) {
+          cnt[ORC_CNT_MOVES_3OPT]++;
           cnt[ORC_CNT_MOVED_ELEMS] += r;
         }
       } else {
@@ -755,7 +855,7 @@ orc_instance *orc_build(const int32_t *xy, int32_t n, const orc_params *p,
   if (!xy || !p || n < 4 || p->cl_size < 2 || p->bl_size < 0 ||
       p->n_ants < 1 || p->min_new_edges < 0 || !(p->rho >= 0.0f) ||
       !(p->rho < 1.0f) || !(p->p_best > 0.0) || !(p->p_best < 1.0) ||
-      p->oropt_max_seg < 1 || p->oropt_max_seg > 64 ||
+      p->oropt_max_seg < 1 || p->oropt_max_seg > 64 || (p->ls_flags & ~15u) ||
       (p->min_new_edges_max > 0 && p->min_new_edges_max < p->min_new_edges))
     return NULL;
   for (int32_t i = 0; i < 2 * n; ++i)
@@ -789,14 +889,15 @@ orc_instance *orc_build(const int32_t *xy, int32_t n, const orc_params *p,
       return NULL;
     }
 
-  /* initial solution: nearest neighbour + LS over all nodes (reading: the
-   * paper adds 3-opt, omitted here) */
+  /* initial solution: nearest neighbour + LS over all nodes (2-opt, Or-opt
+   * when enabled, and 3-opt with ORC_LS_INIT_3OPT) */
   scratch_t S;
   scratch_alloc(&S, n);
   int32_t *all = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   for (int32_t i = 0; i < n; ++i) all[i] = i;
   int64_t len = nearest_neighbour_tour(h, h->gb_route, S.visited);
-  uint32_t init_flags = ORC_LS_2OPT | ORC_LS_SWEEP | (p->ls_flags & ORC_LS_OROPT);
+  uint32_t init_flags =
+      ORC_LS_2OPT | ORC_LS_SWEEP | (p->ls_flags & (ORC_LS_OROPT | ORC_LS_INIT_3OPT));
   len -= local_search(h, h->gb_route, all, n, init_flags, &S, h->init_cnt);
   free(all);
   scratch_free(&S);
@@ -845,7 +946,8 @@ void orc_run(orc_instance *h, int32_t iterations) {
         int64_t len = construct(h, t, (uint64_t)a, route, S.visited, S.chk,
                                 &nchk, cnt);
         if (h->p.ls_flags & (ORC_LS_2OPT | ORC_LS_OROPT))
-          len -= local_search(h, route, S.chk, nchk, h->p.ls_flags, &S, cnt);
+          len -= local_search(h, route, S.chk, nchk, h->p.ls_flags & ~ORC_LS_INIT_3OPT,
+                              &S, cnt);
         h->lens[a] = len;
       }
       scratch_free(&S);

@@ -24,6 +24,7 @@ extern "C" {
 #define ORC_LS_2OPT 1u
 #define ORC_LS_OROPT 2u
 #define ORC_LS_SWEEP 4u
+#define ORC_LS_INIT_3OPT 8u /* initial solution: 3-opt too (Sec. 4.3) */
 
 /* Philox counter "purpose" word */
 #define ORC_PURPOSE_ROULETTE 0u
@@ -45,6 +46,7 @@ enum {
   ORC_CNT_SWEEPS,        /* sweeps over the touched set                 */
   ORC_CNT_CHECKLIST0,    /* checklist length handed to the LS           */
   ORC_CNT_LS_GAIN,       /* total LS gain                               */
+  ORC_CNT_MOVES_3OPT,    /* applied 3-opt moves (initial solution)      */
   ORC_NCNT
 };
 

@@ -12,10 +12,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc_faco.so")
 
-LS_2OPT, LS_OROPT, LS_SWEEP = 1, 2, 4
+LS_2OPT, LS_OROPT, LS_SWEEP, LS_INIT_3OPT = 1, 2, 4, 8
 CNT_NAMES = ["aco_steps", "copied", "backup", "fallback", "new_edges",
              "ls_pops", "moves_2opt", "moves_oropt", "moved_elems", "sweeps",
-             "checklist0", "ls_gain"]
+             "checklist0", "ls_gain", "moves_3opt"]
 NCNT = len(CNT_NAMES)
 
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfaco_hip.so")
 
 FACO_OK, FACO_EINVAL, FACO_EDUP, FACO_ENOMEM, FACO_EDEVICE = 0, -1, -2, -3, -4
-FACO_LS_2OPT, FACO_LS_OROPT, FACO_LS_SWEEP = 1, 2, 4
+FACO_LS_2OPT, FACO_LS_OROPT, FACO_LS_SWEEP, FACO_LS_INIT_3OPT = 1, 2, 4, 8
 (FACO_DBG_ANT_ROUTES, FACO_DBG_ANT_LENGTHS, FACO_DBG_PHEROMONE, FACO_DBG_SOURCE,
  FACO_DBG_LIMITS, FACO_DBG_COUNTERS, FACO_DBG_CAND_LISTS, FACO_DBG_BACKUP_LISTS,
  FACO_DBG_HEURISTIC, FACO_DBG_INFO, FACO_DBG_INIT_COUNTERS,
@@ -23,7 +23,7 @@ FACO_LS_2OPT, FACO_LS_OROPT, FACO_LS_SWEEP = 1, 2, 4
 FACO_FAULT_LS_STALL, FACO_FAULT_LENGTH, FACO_FAULT_PERMUTATION = 1, 2, 4
 CNT_NAMES = ["aco_steps", "copied", "backup", "fallback", "new_edges",
              "ls_pops", "moves_2opt", "moves_oropt", "moved_elems", "sweeps",
-             "checklist0", "ls_gain"]
+             "checklist0", "ls_gain", "moves_3opt"]
 FACO_NCNT = len(CNT_NAMES)
 
 EXPORTED = ["faco_build_instance", "faco_run_iterations", "faco_get_best_tour",

@@ -7,7 +7,7 @@ import math
 
 import numpy as np
 
-LS_2OPT, LS_OROPT, LS_SWEEP = 1, 2, 4
+LS_2OPT, LS_OROPT, LS_SWEEP, LS_INIT_3OPT = 1, 2, 4, 8
 
 
 def philox_word0(seed, ctr):
@@ -56,7 +56,7 @@ class Ref:
             route.append(v)
             vis.add(v)
         self.nn = list(route)
-        init_flags = LS_2OPT | LS_SWEEP | (ls_flags & LS_OROPT)
+        init_flags = LS_2OPT | LS_SWEEP | (ls_flags & (LS_OROPT | LS_INIT_3OPT))
         route = self.local_search(route, list(range(n)), init_flags)
         self.gb = route
         self.gb_len = self.length(route)
@@ -199,6 +199,34 @@ class Ref:
                             g = base + dist(xy, b, e) - dist(xy, a, b) - dist(xy, o, e)
                             if g > best[0]:
                                 best = (g, ("o", seg, p, q, a, b, e))
+        if best[1] is None and flags & LS_INIT_3OPT:
+            best = self.best_3opt(r, pos, a, best)
+        return best
+
+    def best_3opt(self, r, pos, a, best):
+        """Pure 3-opt reconnection (two adjacent blocks exchange places, no
+        reversal) with positive partial gains, both orientations."""
+        n, xy = self.n, self.xy
+        for step in (1, -1):
+            nxt = lambda x: r[(pos[x] + step) % n]
+            ahead = lambda frm, x: ((pos[x] - pos[frm]) * step) % n
+            t1 = a
+            t2 = nxt(t1)
+            for t3 in self.cl[t2]:
+                g1 = dist(xy, t1, t2) - dist(xy, t2, t3)
+                if g1 <= 0 or t3 == t1:
+                    continue
+                t4 = nxt(t3)
+                if t4 == t1:
+                    continue
+                for t5 in self.cl[t4]:
+                    g2 = g1 + dist(xy, t3, t4) - dist(xy, t4, t5)
+                    if g2 <= 0 or ahead(t2, t5) >= ahead(t2, t3):
+                        continue
+                    t6 = nxt(t5)
+                    g = g2 + dist(xy, t5, t6) - dist(xy, t6, t1)
+                    if g > best[0]:
+                        best = (g, ("3", step, t1, t2, t3, t4, t5, t6))
         return best
 
     def apply(self, r, pos, mv):
@@ -213,6 +241,18 @@ class Ref:
                 r[i] = v
                 pos[v] = i
             return [w, x, y, z]
+        if mv[0] == "3":
+            _, step, t1, t2, t3, t4, t5, t6 = mv
+            # array order: the block starting after t1 (succ) or at t3 (pred)
+            first = [t2, t5] if step == 1 else [t3, t6]
+            second = [t6, t3] if step == 1 else [t5, t2]
+            s = pos[first[0]]
+            A = [r[(s + i) % n] for i in range((pos[first[1]] - s) % n + 1)]
+            B = [r[(pos[second[0]] + i) % n] for i in range((pos[second[1]] - pos[second[0]]) % n + 1)]
+            for i, v in enumerate(B + A):
+                r[(s + i) % n] = v
+                pos[v] = (s + i) % n
+            return [t1, t2, t3, t4, t5, t6]
         _, seg, p, q, a, b, e = mv
         L = len(seg)
         if r[(pos[b] + 1) % n] == e:
@@ -278,7 +318,7 @@ class Ref:
             for a in range(self.A):
                 r, chk = self.construct(t, a)
                 if self.flags & (LS_2OPT | LS_OROPT):
-                    r = self.local_search(r, chk, self.flags)
+                    r = self.local_search(r, chk, self.flags & ~LS_INIT_3OPT)
                 routes.append(r)
                 lens.append(self.length(r))
             ib = min(range(self.A), key=lambda a: (lens[a], a))

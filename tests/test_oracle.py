@@ -507,6 +507,116 @@ def _brute_opt(xy):
     return best
 
 
+def _tour_len(xy, r):
+    return sum(_exact_nint_sqrt(int((int(xy[r[i]][0]) - int(xy[r[i - 1]][0])) ** 2 +
+                                    (int(xy[r[i]][1]) - int(xy[r[i - 1]][1])) ** 2))
+               for i in range(len(r)))
+
+
+def _segment_exchange_gains(xy, r):
+    """Every pure 3-opt reconnection of the cycle r (three removed edges at
+    array positions i < j < k, blocks r[i+1..j] and r[j+1..k] exchanged),
+    by brute force."""
+    n = len(r)
+    d = lambda a, b: _exact_nint_sqrt(int((int(xy[a][0]) - int(xy[b][0])) ** 2 +
+                                          (int(xy[a][1]) - int(xy[b][1])) ** 2))
+    for i in range(n):
+        for j in range(i + 1, n):
+            for k in range(j + 1, n):
+                a, b = r[i], r[(i + 1) % n]
+                c, e = r[j], r[(j + 1) % n]
+                f, g = r[k], r[(k + 1) % n]
+                if len({i, j, k}) < 3 or (k + 1) % n == i:
+                    continue
+                yield d(a, b) + d(c, e) + d(f, g) - d(a, e) - d(f, b) - d(c, g)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_full_list_3opt_leaves_no_improving_exchange(seed):
+    """With full candidate lists and every city checked until a sweep finds
+    nothing, the positive-partial-gain search is complete: no pure 3-opt
+    reconnection and no 2-opt move over all triples and pairs improves."""
+    n = 9 + seed % 4
+    xy = I.uniform(n, 50 + seed)
+    o = O.Oracle(xy, cl_size=n - 1, bl_size=0, n_ants=1)
+    route, _ = o.nearest_neighbour()
+    flags = O.LS_2OPT | O.LS_INIT_3OPT | O.LS_SWEEP
+    out, gain, cnt = o.local_search(route, np.arange(n, dtype=np.int32), flags)
+    moves = cnt[O.CNT_NAMES.index("moves_2opt")] + cnt[O.CNT_NAMES.index("moves_3opt")]
+    assert moves < n            # Alg. 3's cap of n changes was not reached
+    r = out.tolist()
+    assert sorted(r) == list(range(n))
+    assert _tour_len(xy, route.tolist()) - _tour_len(xy, r) == gain
+    assert max(_segment_exchange_gains(xy, r), default=0) <= 0
+    for i in range(n):
+        for j in range(i + 2, n):
+            a, b, c, e = r[i], r[i + 1], r[j], r[(j + 1) % n]
+            if e == a:
+                continue
+            dd = lambda u, v: O.dist(xy, u, v)
+            assert dd(a, b) + dd(c, e) - dd(a, c) - dd(b, e) <= 0
+
+
+def _defined_3opt_gain(o, xy, r, a):
+    """The 3-opt neighbourhood of a as defined (positive partial gains over
+    the candidate lists, both orientations), enumerated pair by pair."""
+    n = len(r)
+    pos = {v: i for i, v in enumerate(r)}
+    cl, _ = o.lists()
+    d = lambda u, v: O.dist(xy, u, v)
+    best = 0
+    for step in (1, -1):
+        t2 = r[(pos[a] + step) % n]
+        for t3 in cl[t2]:
+            t3 = int(t3)
+            t4 = r[(pos[t3] + step) % n]
+            for t5 in cl[t4]:
+                t5 = int(t5)
+                t6 = r[(pos[t5] + step) % n]
+                g1 = d(a, t2) - d(t2, t3)
+                g2 = g1 + d(t3, t4) - d(t4, t5)
+                off = lambda x: ((pos[x] - pos[t2]) * step) % n
+                if t3 == a or t4 == a or g1 <= 0 or g2 <= 0 or off(t5) >= off(t3):
+                    continue
+                best = max(best, g2 + d(t5, t6) - d(t6, a))
+    return best
+
+
+def test_3opt_sweep_leaves_no_improving_move_from_listed_cities():
+    xy = I.make_points("cluster16", 220, 77)
+    o = O.Oracle(xy, cl_size=8, n_ants=1)
+    rng = np.random.default_rng(4)
+    route, _ = o.nearest_neighbour()
+    chk = rng.choice(len(xy), size=60, replace=False).astype(np.int32)
+    flags = O.LS_2OPT | O.LS_OROPT | O.LS_INIT_3OPT | O.LS_SWEEP
+    out, gain, cnt = o.local_search(route, chk, flags)
+    assert _tour_len(xy, route.tolist()) - _tour_len(xy, out.tolist()) == gain
+    assert cnt[O.CNT_NAMES.index("moves_3opt")] > 0
+    moves = sum(cnt[O.CNT_NAMES.index(c)] for c in ("moves_2opt", "moves_oropt", "moves_3opt"))
+    assert moves < len(xy)      # Alg. 3's cap of n changes was not reached
+    r = out.tolist()
+    # every listed city is left without an improving move (the sweep)
+    for a in set(chk.tolist()):
+        assert o.best_move_gain(out, a, flags) == 0
+        assert _defined_3opt_gain(o, xy, r, a) <= 0
+
+
+def test_initial_solution_with_3opt():
+    """The initial solution's search with 3-opt (Sec. 4.3): a permutation,
+    its length recomputed, 3-opt moves made, and no city has a move left."""
+    xy = I.make_points("uniform", 400, 12)
+    o = O.Oracle(xy, n_ants=2, ls_flags=15)
+    tour, L = o.best()
+    assert sorted(tour.tolist()) == list(range(400))
+    assert L == O.tour_length(xy, tour)
+    assert o.init_counters()[O.CNT_NAMES.index("moves_3opt")] > 0
+    flags = O.LS_2OPT | O.LS_OROPT | O.LS_INIT_3OPT
+    assert all(o.best_move_gain(tour, a, flags) == 0 for a in range(400))
+    # the ants' own search never uses 3-opt
+    o.run(2)
+    assert (o.ant_counters()[:, O.CNT_NAMES.index("moves_3opt")] == 0).all()
+
+
 def test_tiny_instances_against_brute_force():
     hits, total = 0, 0
     for seed in range(24):

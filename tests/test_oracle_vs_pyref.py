@@ -20,6 +20,11 @@ CASES = [
                             ls_flags=O.LS_OROPT | O.LS_SWEEP, oropt_max_seg=2)),
     (34, "cluster16", 7, dict(cl_size=6, bl_size=4, n_ants=5, min_new_edges=1, rho=0.4,
                               min_new_edges_max=9)),
+    # initial solution with 3-opt
+    (38, "uniform", 8, dict(cl_size=7, bl_size=4, n_ants=4, min_new_edges=3, rho=0.5,
+                            ls_flags=15)),
+    (30, "cluster16", 9, dict(cl_size=5, bl_size=3, n_ants=3, min_new_edges=2, rho=0.5,
+                              ls_flags=O.LS_2OPT | O.LS_SWEEP | O.LS_INIT_3OPT)),
 ]
 
 
@@ -54,7 +59,8 @@ def test_local_search_arrays_match_python_statement():
     n = 45
     xy = I.make_points("cluster16", n, 9)
     for flags in (O.LS_2OPT, O.LS_2OPT | O.LS_SWEEP, O.LS_2OPT | O.LS_OROPT | O.LS_SWEEP,
-                  O.LS_OROPT):
+                  O.LS_OROPT, O.LS_2OPT | O.LS_INIT_3OPT | O.LS_SWEEP,
+                  O.LS_2OPT | O.LS_OROPT | O.LS_INIT_3OPT | O.LS_SWEEP):
         o = O.Oracle(xy, cl_size=8, ls_flags=flags)
         r = pyref.Ref(xy, cl_size=8, ls_flags=flags)
         rng = np.random.default_rng(flags)
