@@ -42,6 +42,9 @@ extern "C" {
 #define FACO_LS_2OPT 1u  /* 2-opt moves of Alg. 3                         */
 #define FACO_LS_OROPT 2u /* Or-opt segment insertion (not in the paper)   */
 #define FACO_LS_SWEEP 4u /* re-examine every listed node until none improves */
+#define FACO_LS_INIT_3OPT 8u /* the initial solution's search also tries 3-opt
+                                (Sec. 4.3: nearest neighbour improved with
+                                2-opt and 3-opt); ants never use it        */
 
 /* Parameters (Table 1 of the paper; names follow it). */
 typedef struct faco_params {
@@ -230,6 +233,7 @@ enum {
   FACO_CNT_SWEEPS,
   FACO_CNT_CHECKLIST0,
   FACO_CNT_LS_GAIN,
+  FACO_CNT_MOVES_3OPT,   /* 3-opt moves (initial solution only)          */
   FACO_NCNT
 };
 int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t bytes);

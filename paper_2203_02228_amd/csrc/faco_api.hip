@@ -18,6 +18,7 @@
 #include "../../include/faco.h"
 #include "ant_kernels.hpp"
 #include "faco_aux.hpp"
+#include "faco_init.hpp"
 
 using faco::DevState;
 using faco::Inst;
@@ -79,7 +80,7 @@ static const char *validate(const faco_params *p, int32_t n) {
   if (!(p->p_best > 0.0) || !(p->p_best < 1.0)) return "p_best must be in (0, 1)";
   if (!(p->p_source_gbest >= 0.0) || !(p->p_source_gbest <= 1.0))
     return "p_source_gbest must be in [0, 1]";
-  if (p->ls_flags & ~7u) return "unknown ls_flags bits";
+  if (p->ls_flags & ~15u) return "unknown ls_flags bits";
   if (p->oropt_max_seg < 1 || p->oropt_max_seg > faco::kMaxOrSeg)
     return "oropt_max_seg must be in [1, 3]";
   return nullptr;
@@ -449,6 +450,13 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   // initial solution (ant slot 0), limits, tau = tau_max, source = global best
   hipLaunchKernelGGL(faco_ant_kernel(h->k, h->tw), dim3(1), dim3(64 * h->tw), h->lds_ant,
                      h->stream, I, 1);
+  if (p->ls_flags & FACO_LS_INIT_3OPT) {
+    // the initial search with 3-opt, on the nearest-neighbour tour
+    const size_t ilds = sizeof(uint32_t) * 2 * ((N + 31) / 32);
+    BTRY(hipFuncSetAttribute((const void *)faco::init_search_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)ilds));
+    hipLaunchKernelGGL(faco::init_search_kernel, dim3(1), dim3(64), ilds, h->stream, I);
+  }
   hipLaunchKernelGGL(faco::init_state_kernel, dim3(1), dim3(1), 0, h->stream, I);
   hipLaunchKernelGGL(faco::source_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      h->stream, I, 1);

@@ -16,7 +16,7 @@ struct DevState {
   int32_t src_gb;    // 1 if the last source choice took the global best
   int32_t improved;  // 1 if the last iteration improved the global best
   int32_t dup;       // set by the list kernel when two cities coincide
-  int64_t init_cnt[12];
+  int64_t init_cnt[13];
   // Faults found on the device (FAULT_* bits; the first one's ant and
   // iteration), and the number of tours the verification kernel has checked.
   int32_t fault, fault_ant;
@@ -103,10 +103,11 @@ enum {
   CNT_SWEEPS,
   CNT_CHECKLIST0,
   CNT_LS_GAIN,
+  CNT_MOVES_3OPT,
   NCNT
 };
 
-constexpr uint32_t LS_2OPT = 1u, LS_OROPT = 2u, LS_SWEEP = 4u;
+constexpr uint32_t LS_2OPT = 1u, LS_OROPT = 2u, LS_SWEEP = 4u, LS_INIT_3OPT = 8u;
 constexpr int kMaxCl = 32;
 constexpr int kMaxBl = 64;
 constexpr int kMaxOrSeg = 3;

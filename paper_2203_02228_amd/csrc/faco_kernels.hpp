@@ -1778,7 +1778,8 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
     // the initial solution reports only its local-search counters
 #pragma unroll
     for (int c = 0; c < CNT_LS_POPS; ++c) cnt[c] = 0;
-    flags = LS_2OPT | LS_SWEEP | (I.ls_flags & LS_OROPT);
+    // with 3-opt, the initial search runs in init_search_kernel afterwards
+    flags = (I.ls_flags & LS_INIT_3OPT) ? 0u : (LS_2OPT | LS_SWEEP | (I.ls_flags & LS_OROPT));
     Q.in_lds = n <= lcap ? 1 : 0;
     Q.cap = Q.in_lds ? lcap : n;
     // every city listed, in ascending original number

@@ -78,6 +78,10 @@ SMALL = [
     (257, "uniform", 9, dict(n_ants=7, min_new_edges=6, rho=0.9, p_source_gbest=0.5)),
     # calc_num_new_edges() drawn per ant from a range
     (300, "cluster16", 10, dict(n_ants=9, min_new_edges=2, min_new_edges_max=25)),
+    # initial solution with 3-opt (2-opt + Or-opt + 3-opt), and without Or-opt
+    (400, "uniform", 11, dict(n_ants=6, min_new_edges=8, ls_flags=15)),
+    (150, "cluster16", 12, dict(n_ants=5, min_new_edges=4, cl_size=6, ls_flags=13)),
+    (9, "uniform", 13, dict(n_ants=4, min_new_edges=2, ls_flags=15)),
 ]
 
 

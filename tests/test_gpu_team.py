@@ -25,6 +25,7 @@ CASES = [
     (3000, "cluster16", 12, dict(n_ants=8, min_new_edges=40)),
     (6000, "uniform", 14, dict(n_ants=6, min_new_edges=24, rho=0.8)),
     (4000, "cluster16", 15, dict(n_ants=7, min_new_edges=4, min_new_edges_max=60)),
+    (2500, "uniform", 16, dict(n_ants=6, min_new_edges=12, ls_flags=15)),
 ]
 
 
