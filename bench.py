@@ -181,21 +181,14 @@ def run_batch_mode(args):
     pts = gen_points_parallel([(w.kind, w.n, w.instance_seed) for w in ws])
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    best = {}
-    for apb in (1, 2, 4):  # autotune ants per workgroup on a short run
-        F.faco_set_batch_ants_per_block(apb)
-        hs = [F.faco_build_instance(p, stream=stream, **w.params()) for p, w in zip(pts, ws)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        F.faco_run_batch(hs, 10, stream=stream)
-        torch.cuda.synchronize()
-        best[apb] = round(time.perf_counter() - t0, 4)
-        for h in hs:
-            h.close()
-    apb = min(best, key=best.get)
-    F.faco_set_batch_ants_per_block(apb)
-    log(f"batch autotune {best} -> ants/block {apb}")
     hs = [F.faco_build_instance(p, stream=stream, **w.params()) for p, w in zip(pts, ws)]
+    torch.cuda.synchronize()
+    # the library's autotuner times every configuration on twins of the batch
+    # and stores the fastest for this size class
+    t0 = time.perf_counter()
+    tuned = F.faco_autotune_batch(hs, trial_iterations=args.tune_iterations, stream=stream)
+    tune_s = time.perf_counter() - t0
+    log(f"batch autotune ({tune_s:.1f} s) -> {tuned}")
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -220,7 +213,7 @@ def run_batch_mode(args):
     res_seq = [F.faco_get_best_tour(h)[1] for h in hs]
     for h in hs:
         h.close()
-    F.faco_set_batch_ants_per_block(1)
+    F.faco_set_batch_config()   # forget the tuned choice
     same = res_seq == res_batch[:sub]
     return {
         "metric": "batched solves/s (256 uneven instances, 300 iterations each)",
@@ -231,7 +224,7 @@ def run_batch_mode(args):
         "config": {"workload": "batch256", "instances": len(ws),
                    "n_range": [min(w.n for w in ws), max(w.n for w in ws)],
                    "ants": 16, "cl_size": 12, "min_new_edges": 8, "rho": 0.5,
-                   "ants_per_block": apb, "autotune_s": best},
+                   "tuned": tuned, "autotune_s": round(tune_s, 2)},
         "one_launch_per_instance": {"solves_per_s": round(sub / t_seq, 3), "instances": sub,
                                     "speedup": round((len(ws) / t_batch) / (sub / t_seq), 2),
                                     "identical_lengths": bool(same)},
@@ -286,6 +279,23 @@ def run_served_mode(args):
         h.close()
         same = same and (L == lengths[i])
     seq_rate = len(sample) / sum(svc)
+    # where each request's latency went: admission wait, build, resident run
+    stages = {}
+    for name, lo, hi in (("all", 0, 1 << 30), ("n<8000", 0, 8000), ("8000<=n<40000", 8000, 40000),
+                         ("n>=40000", 40000, 1 << 30)):
+        rs = [r for r in done if lo <= len(r.xy) < hi]
+        if not rs:
+            continue
+        part = {}
+        for key, f in (("wait", lambda r: r.admitted - r.arrival),
+                       ("build", lambda r: r.built - r.admitted),
+                       ("run", lambda r: r.finished - r.built),
+                       ("total", lambda r: r.finished - r.arrival)):
+            v = np.array([f(r) for r in rs])
+            part[key] = {"mean": round(float(v.mean()), 2), "p50": round(float(np.percentile(v, 50)), 2),
+                         "p99": round(float(np.percentile(v, 99)), 2)}
+        part["requests"] = len(rs)
+        stages[name] = part
     return {
         "solves_per_s": round(count / makespan, 3),
         "p50_latency_s": round(lat["p50_s"], 3), "p99_latency_s": round(lat["p99_s"], 3),
@@ -295,6 +305,7 @@ def run_served_mode(args):
         "identical_lengths": bool(same),
         "n_range": [min(w.n for _, w in reqs), max(w.n for _, w in reqs)],
         "errors": len(srv.errors),
+        "latency_stages_s": stages,
     }
 
 
@@ -354,6 +365,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-iterations", type=int, default=0)
     ap.add_argument("--batch-seq-count", type=int, default=32)
+    ap.add_argument("--tune-iterations", type=int, default=10)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--chunk", type=int, default=10)
@@ -497,7 +509,7 @@ def main():
         log("batch256 ...")
         b = run_batch_mode(args)
         out["batched"] = {"solves_per_s": b["value"], "ms_per_iteration": b["ms_per_step"],
-                          "ants_per_block": b["config"]["ants_per_block"],
+                          "tuned": b["config"]["tuned"],
                           "one_launch_per_instance": b["one_launch_per_instance"]}
     if not args.no_served:
         log(f"served: {args.requests} requests at {args.rate}/s ...")

@@ -148,9 +148,56 @@ int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
 int faco_run_batch_noalloc(faco_instance *const *hs, int32_t count, int32_t iterations,
                            void *hip_stream);
 
-/* Ants (wavefronts) per workgroup in faco_run_batch launches with one wave
- * per ant: 1, 2 or 4, lowered when their LDS would not fit a CU (process-
- * wide; an execution-shape choice that never changes results).
+/* How faco_run_batch launches a batch (execution shape only: no setting
+ * changes a result). */
+typedef struct faco_batch_config {
+  int32_t persistent;         /* 1: one persistent launch runs every iteration
+                                 of every instance; each instance's ants of
+                                 the next iteration start as soon as its own
+                                 colony and pheromone update is done
+                                 (device-side phase counters per instance),
+                                 largest tours first.  0: one launch per
+                                 phase over all instances, one iteration
+                                 captured as a HIP graph and replayed.
+                                 Instances with verification on run per
+                                 phase.                                     */
+  int32_t team_waves;         /* waves per ant: 0 = by size (as for a lone
+                                 instance, counting the batch's longest tour
+                                 and all its ants), else 1, 4 or 8          */
+  int32_t ants_per_block;     /* one-wave ants per workgroup: 1, 2 or 4,
+                                 lowered when their LDS would not fit a CU  */
+  int32_t queue_lds_capacity; /* LDS part of each ant's work queue: 0 = as
+                                 built, else 64..16384                       */
+  int32_t big_percent;        /* 0: one batch.  1..100: that share of the
+                                 instances, longest tours first, runs as a
+                                 sub-batch of its own (per phase, waves per
+                                 ant big_team_waves) on a second stream
+                                 beside the rest; the call stays ordered on
+                                 hip_stream                                 */
+  int32_t big_team_waves;     /* 1, 4 or 8 when big_percent > 0              */
+} faco_batch_config;
+
+/* The process-wide default configuration of faco_run_batch (initially per
+ * phase, sizes by the library's rule, one ant per workgroup, queues as
+ * built).  Setting it forgets the configurations faco_autotune_batch
+ * stored.  Errors: FACO_EINVAL. */
+int faco_set_batch_config(const faco_batch_config *config);
+int faco_get_batch_config(faco_batch_config *config);
+
+/* Autotuner: times faco_run_batch over `trial_iterations` iterations with
+ * each candidate configuration (per phase with 1/4/8 waves per ant, 1/2 ants
+ * per workgroup for one-wave ants, LDS queue capacity as built or 2048;
+ * persistent with 4/8-wave teams; the largest 15% or 30% of the instances
+ * split off with 4-wave teams) on twins of the handles built from their own
+ * inputs (the handles do not advance), keeps the fastest, and stores it for the batch's size class
+ * (the longest tour's power of two): later faco_run_batch calls whose
+ * longest tour falls in the same class use it.  best_out (may be NULL)
+ * receives it.  Synchronises hip_stream.
+ * Errors: FACO_EINVAL, FACO_ENOMEM, FACO_EDEVICE. */
+int faco_autotune_batch(faco_instance *const *hs, int32_t count, int32_t trial_iterations,
+                        void *hip_stream, faco_batch_config *best_out);
+
+/* Ants per workgroup of the default configuration (1, 2 or 4).
  * Errors: FACO_EINVAL. */
 int faco_set_batch_ants_per_block(int32_t ants_per_block);
 

@@ -133,6 +133,32 @@ FACO_DEV void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// -------------------------------------------- device-wide coordination ---
+// Relaxed atomics at agent (device) scope, and the fences that order plain
+// memory accesses around them (a release fence before publishing, an acquire
+// fence after observing).
+
+FACO_DEV int ld_agent(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+FACO_DEV void st_agent(int *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+FACO_DEV int add_agent(int *p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+FACO_DEV int64_t ld_agent64(const int64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// compare-and-swap; returns the value found
+FACO_DEV int64_t cas_agent64(int64_t *p, int64_t expected, int64_t desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return expected;
+}
+FACO_DEV void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+FACO_DEV void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
 // --------------------------------------------------------------- bitmap ---
 
 FACO_DEV bool bit_get(const uint32_t *bm, int x) {

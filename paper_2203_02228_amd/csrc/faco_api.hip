@@ -39,6 +39,7 @@ struct faco_instance {
   int tw = 1;  // waves per ant in the per-instance ant kernel
   int device = 0;  // the device current at build
   std::vector<int32_t> orig_of, int_of;  // internal label <-> original city number
+  std::vector<int32_t> xy_host;          // the build's coordinates (autotuner twins)
   bool timing = false;
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> ev_pool;  // timing events, created once and reused
@@ -310,6 +311,7 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   faco_instance *h = new faco_instance();
   h->p = *p;
   h->n = n;
+  h->xy_host.assign(xy, xy + 2 * (size_t)n);
   effective_sizes(n, p, &h->k, &h->bl);
   h->stream = (hipStream_t)hip_stream;
   if (hipGetDevice(&h->device) != hipSuccess) {
@@ -391,6 +393,10 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   }
   BTRY(hipMemsetAsync(I.st, 0, sizeof(DevState), h->stream));
   BTRY(hipMemsetAsync(I.cnt_acc, 0, sizeof(int64_t) * A * faco::NCNT, h->stream));
+  // ant state before the first iteration: no tours (-1), lengths and counters 0
+  BTRY(hipMemsetAsync(I.routes, 0xFF, sizeof(int32_t) * N * A, h->stream));
+  BTRY(hipMemsetAsync(I.lens, 0, sizeof(int64_t) * A, h->stream));
+  BTRY(hipMemsetAsync(I.cnt, 0, sizeof(int64_t) * A * faco::NCNT, h->stream));
   BTRY(hipMemsetAsync(I.ticks, 0, sizeof(int64_t) * A * 16, h->stream));
   BTRY(hipMemsetAsync(I.vsum, 0, sizeof(int64_t) * (A + 1), h->stream));
   BTRY(hipMemsetAsync(I.vbad, 0, sizeof(int32_t) * (A + 1), h->stream));
@@ -607,7 +613,7 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
   // back to original city numbers: city values, and rows indexed by city
   const auto &orig = h->orig_of;
   auto map_values = [&](int32_t *v, size_t cnt) {
-    for (size_t i = 0; i < cnt; ++i) v[i] = orig[(size_t)v[i]];
+    for (size_t i = 0; i < cnt; ++i) v[i] = (uint32_t)v[i] < (uint32_t)N ? orig[(size_t)v[i]] : -1;
   };
   auto permute_rows = [&](void *base, size_t row_bytes) {
     std::vector<unsigned char> tmp((unsigned char *)base, (unsigned char *)base + N * row_bytes);
@@ -669,27 +675,82 @@ extern "C" int faco_phase_times(faco_instance *h, double *ms_out, int64_t *launc
 }
 
 // ------------------------------------------------------------------------
-// Batched execution (faco_run_batch).  The launch tables live in a
-// process-wide workspace that grows on demand; calls are serialised.
-
+// Batched execution (faco_run_batch).  The launch tables live in a workspace
+// per stream that grows on demand; calls are serialised.  How a batch is
+// launched (one persistent launch or launches per phase, waves per ant, ants
+// per workgroup, LDS queue capacity) is a faco_batch_config: the one
+// faco_autotune_batch stored for the batch's size class, else the
+// process-wide default.  None of it changes a result.
 
 static const size_t kLdsBytes = 160 * 1024;  // LDS of one CU (gfx950)
 static std::mutex g_batch_mu;
-static int g_batch_apb = 1;  // ants (waves) per workgroup in batched launches
+static faco_batch_config g_batch_cfg = {0, 0, 1, 0, 0, 0};
+// tuned configurations by size class (log2 of the longest tour)
+static std::map<int, faco_batch_config> g_tuned;
+
 struct BatchWs {
   Inst *insts = nullptr;
   int2 *amap = nullptr;
-  size_t cap_insts = 0, cap_amap = 0;
+  faco::BatchCtl *ctl = nullptr;
+  faco::BatchRun *run = nullptr;
+  size_t cap_insts = 0, cap_amap = 0, cap_ctl = 0;
   hipEvent_t last_done = nullptr;  // completion of the previous batch
 };
 // one workspace per stream, so batches on different streams run concurrently
 static std::map<hipStream_t, BatchWs> g_ws_map;
 
+static const char *check_config(const faco_batch_config *c) {
+  if (!c) return "config is NULL";
+  if (c->persistent != 0 && c->persistent != 1) return "persistent must be 0 or 1";
+  if (c->team_waves != 0 && c->team_waves != 1 && c->team_waves != 4 && c->team_waves != 8)
+    return "team_waves must be 0, 1, 4 or 8";
+  if (c->ants_per_block != 1 && c->ants_per_block != 2 && c->ants_per_block != 4)
+    return "ants_per_block must be 1, 2 or 4";
+  if (c->queue_lds_capacity != 0 &&
+      (c->queue_lds_capacity < 64 || c->queue_lds_capacity > faco::kLdsRingMax))
+    return "queue_lds_capacity must be 0 or in [64, 16384]";
+  if (c->big_percent < 0 || c->big_percent > 100) return "big_percent must be in [0, 100]";
+  if (c->big_percent > 0 && c->big_team_waves != 1 && c->big_team_waves != 4 &&
+      c->big_team_waves != 8)
+    return "big_team_waves must be 1, 4 or 8";
+  return nullptr;
+}
+
+extern "C" int faco_set_batch_config(const faco_batch_config *c) {
+  if (const char *m = check_config(c)) return set_err(nullptr, FACO_EINVAL, m);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batch_cfg = *c;
+  g_tuned.clear();
+  return FACO_OK;
+}
+
+extern "C" int faco_get_batch_config(faco_batch_config *c) {
+  if (!c) return set_err(nullptr, FACO_EINVAL, "config is NULL");
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  *c = g_batch_cfg;
+  return FACO_OK;
+}
+
 extern "C" int faco_set_batch_ants_per_block(int32_t apb) {
   if (apb != 1 && apb != 2 && apb != 4) return set_err(nullptr, FACO_EINVAL, "ants per block must be 1, 2 or 4");
   std::lock_guard<std::mutex> lk(g_batch_mu);
-  g_batch_apb = apb;
+  g_batch_cfg.ants_per_block = apb;
   return FACO_OK;
+}
+
+static int ilog2(int64_t v) {
+  int r = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++r;
+  }
+  return r;
+}
+
+static int size_class(faco_instance *const *hs, int32_t count) {
+  int maxn = 0;
+  for (int32_t i = 0; i < count; ++i) maxn = hs[i]->n > maxn ? hs[i]->n : maxn;
+  return ilog2(maxn);
 }
 
 // Argument checks shared by the batched entry points.
@@ -714,40 +775,56 @@ static int batch_ant_count(faco_instance *const *hs, int32_t count) {
 // Launch shape of one batch.
 struct BatchShape {
   int count = 0, total = 0, kmax = 2, maxn = 0, max_ants = 0, tw = 1, apb = 1;
-  bool any_verify = false;
+  bool any_verify = false, persistent = false;
   size_t lds_words = 0, max_slots = 0, lds_bytes = 0;
   AntBatchFn antk = nullptr;
+  AntPersistFn persk = nullptr;
 };
 
 // Fill the host tables (insts[count], amap[total ants]) and derive the
-// launch shape.  Caller holds g_batch_mu.
+// launch shape from the configuration.  Caller holds g_batch_mu.
 static void batch_shape(faco_instance *const *hs, int32_t count, Inst *insts, int2 *amap,
-                        BatchShape &B) {
+                        const faco_batch_config &cfg, BatchShape &B) {
   B.count = count;
-  int w = 0;
   for (int32_t i = 0; i < count; ++i) {
     faco_instance *h = hs[i];
-    insts[i] = h->dv;
     B.kmax = h->k > B.kmax ? h->k : B.kmax;
     B.maxn = h->n > B.maxn ? h->n : B.maxn;
     B.max_ants = h->p.n_ants > B.max_ants ? h->p.n_ants : B.max_ants;
     B.any_verify = B.any_verify || h->dv.verify;
-    const size_t words = 3 * (size_t)((h->n + 31) / 32) + (size_t)h->dv.lcap;
+    B.total += h->p.n_ants;
+  }
+  // waves per ant: the configuration's, else as for a lone instance (from
+  // the longest tour and the ant count)
+  B.tw = cfg.team_waves ? cfg.team_waves : team_waves_for(B.maxn, B.total);
+  int w = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    faco_instance *h = hs[i];
+    insts[i] = h->dv;
+    if (cfg.queue_lds_capacity) {
+      // the queue's LDS part: the configured capacity, within what LDS has
+      // left beside the team area and the three bitmaps
+      const int room = 160 * 1024 / 4 - faco_team_lds_words(8) - 3 * ((h->n + 31) / 32);
+      int cap = h->n < cfg.queue_lds_capacity ? h->n : cfg.queue_lds_capacity;
+      insts[i].lcap = cap < room ? cap : room;
+    }
+    const size_t words = 3 * (size_t)((h->n + 31) / 32) + (size_t)insts[i].lcap;
     B.lds_words = words > B.lds_words ? words : B.lds_words;
     const size_t slots = (size_t)h->n * (size_t)h->k;
     B.max_slots = slots > B.max_slots ? slots : B.max_slots;
-    for (int a = 0; a < h->p.n_ants; ++a) amap[w++] = make_int2(i, a);
+    if (amap)
+      for (int a = 0; a < h->p.n_ants; ++a) amap[w++] = make_int2(i, a);
   }
-  B.total = w;
-  // waves per ant (as for a lone instance, from the largest tour and the
-  // ant count); with one wave per ant, ants per workgroup: the setting,
+  // with one wave per ant, ants per workgroup: the configured number,
   // lowered until their LDS fits a CU
-  B.tw = team_waves_for(B.maxn, B.total);
-  B.apb = B.tw > 1 ? 1 : g_batch_apb;
+  B.apb = B.tw > 1 ? 1 : cfg.ants_per_block;
   while (B.apb > 1 && sizeof(uint32_t) * B.lds_words * (size_t)B.apb > kLdsBytes) B.apb >>= 1;
   B.lds_bytes =
       sizeof(uint32_t) * ((size_t)faco_team_lds_words(B.tw) + B.lds_words * (size_t)B.apb);
   B.antk = faco_ant_batch_kernel(B.kmax, B.tw);
+  B.persk = faco_ant_persist_kernel(B.kmax, B.tw);
+  // the per-iteration verification runs in the per-phase launches
+  B.persistent = cfg.persistent == 1 && !B.any_verify;
 }
 
 // The launches of one batched iteration over the device tables.
@@ -772,13 +849,22 @@ static void enqueue_batch_iteration(const BatchShape &B, const Inst *d_insts,
   hipLaunchKernelGGL(faco::pheromone_batch_kernel, g_tau, dim3(256), 0, s, d_insts);
 }
 
-extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
-                              void *hip_stream) {
-  if (const char *m = check_batch_args(hs, count, iterations))
-    return set_err(nullptr, FACO_EINVAL, m);
-  if (count == 0 || iterations == 0) return FACO_OK;
-  std::lock_guard<std::mutex> lk(g_batch_mu);
-  hipStream_t st = (hipStream_t)hip_stream;
+// Grow a workspace array (the previous batch on the stream has finished).
+template <class T>
+static hipError_t ws_grow(T *&ptr, size_t &cap, size_t want) {
+  if (cap >= want) return hipSuccess;
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  const hipError_t e = hipMalloc((void **)&ptr, sizeof(T) * want);
+  if (e == hipSuccess) cap = want;
+  return e;
+}
+
+// One batch call with an explicit configuration.
+// One (sub-)batch with an explicit configuration.  Caller holds g_batch_mu.
+static int run_batch_one(faco_instance *const *hs, int32_t count, int32_t iterations,
+                         hipStream_t st, const faco_batch_config &cfg) {
   BatchWs &g_ws = g_ws_map[st];
   hipError_t e;
 #define BT(expr)                                                                      \
@@ -788,28 +874,22 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
   std::vector<Inst> insts((size_t)count);
   std::vector<int2> amap((size_t)batch_ant_count(hs, count));
   BatchShape B;
-  batch_shape(hs, count, insts.data(), amap.data(), B);
+  batch_shape(hs, count, insts.data(), amap.data(), cfg, B);
   const int total = B.total;
   // the tables are shared: the previous batch must be done with them
   if (!g_ws.last_done) BT(hipEventCreateWithFlags(&g_ws.last_done, hipEventDisableTiming));
-  const bool grow = g_ws.cap_insts < (size_t)count || g_ws.cap_amap < (size_t)total;
+  const bool grow = g_ws.cap_insts < (size_t)count || g_ws.cap_amap < (size_t)total ||
+                    g_ws.cap_ctl < (size_t)count || !g_ws.run;
   if (grow) BT(hipEventSynchronize(g_ws.last_done));
   BT(hipStreamWaitEvent(st, g_ws.last_done, 0));
   // device tables
-  std::unique_lock<std::mutex> alloc_lk(g_capture_mu);
-  if (g_ws.cap_insts < (size_t)count) {
-    if (g_ws.insts) (void)hipFree(g_ws.insts);
-    g_ws.insts = nullptr;
-    BT(hipMalloc((void **)&g_ws.insts, sizeof(Inst) * (size_t)count));
-    g_ws.cap_insts = (size_t)count;
+  {
+    std::lock_guard<std::mutex> alloc_lk(g_capture_mu);
+    BT(ws_grow(g_ws.insts, g_ws.cap_insts, (size_t)count));
+    BT(ws_grow(g_ws.amap, g_ws.cap_amap, (size_t)total));
+    BT(ws_grow(g_ws.ctl, g_ws.cap_ctl, (size_t)count));
+    if (!g_ws.run) BT(hipMalloc((void **)&g_ws.run, sizeof(faco::BatchRun)));
   }
-  if (g_ws.cap_amap < (size_t)total) {
-    if (g_ws.amap) (void)hipFree(g_ws.amap);
-    g_ws.amap = nullptr;
-    BT(hipMalloc((void **)&g_ws.amap, sizeof(int2) * (size_t)total));
-    g_ws.cap_amap = (size_t)total;
-  }
-  alloc_lk.unlock();
   // order after the handles' own streams
   for (int32_t i = 0; i < count; ++i) {
     if (hs[i]->stream == st) continue;
@@ -819,38 +899,210 @@ extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t i
     BT(hipStreamWaitEvent(st, ev, 0));
     BT(hipEventDestroy(ev));
   }
-  BT(hipMemcpyAsync(g_ws.insts, insts.data(), sizeof(Inst) * (size_t)count,
-                    hipMemcpyHostToDevice, st));
-  BT(hipMemcpyAsync(g_ws.amap, amap.data(), sizeof(int2) * (size_t)total,
-                    hipMemcpyHostToDevice, st));
-  BT(hipFuncSetAttribute((const void *)B.antk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                         (int)B.lds_bytes));
-  if (iterations == 1) {
-    enqueue_batch_iteration(B, g_ws.insts, g_ws.amap, st);
+  if (B.persistent) {
+    // largest tours first: their ants are the longest chains
+    std::vector<int> order((size_t)count);
+    for (int32_t i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return hs[a]->n > hs[b]->n; });
+    std::vector<Inst> sorted((size_t)count);
+    std::vector<faco::BatchCtl> ctl((size_t)count);
+    for (int32_t j = 0; j < count; ++j) {
+      sorted[(size_t)j] = insts[(size_t)order[(size_t)j]];
+      ctl[(size_t)j] = faco::BatchCtl{0, 0, 0, hs[order[(size_t)j]]->p.n_ants, 0};
+    }
+    const faco::BatchRun run = {count, iterations, 0, 0};
+    BT(hipMemcpyAsync(g_ws.insts, sorted.data(), sizeof(Inst) * (size_t)count,
+                      hipMemcpyHostToDevice, st));
+    BT(hipMemcpyAsync(g_ws.ctl, ctl.data(), sizeof(faco::BatchCtl) * (size_t)count,
+                      hipMemcpyHostToDevice, st));
+    BT(hipMemcpyAsync(g_ws.run, &run, sizeof(run), hipMemcpyHostToDevice, st));
+    BT(hipFuncSetAttribute((const void *)B.persk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)B.lds_bytes));
+    // as many workers as can be resident, at most one per ant
+    const int threads = 64 * (B.tw > 1 ? B.tw : B.apb);
+    int per_cu = 0, dev = 0, ncu = 0;
+    BT(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)B.persk, threads,
+                                                    B.lds_bytes));
+    BT(hipGetDevice(&dev));
+    BT(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int want = B.tw > 1 ? total : (total + B.apb - 1) / B.apb;
+    int grid = (per_cu > 0 ? per_cu : 1) * (ncu > 0 ? ncu : 1);
+    grid = grid < want ? grid : want;
+    hipLaunchKernelGGL(B.persk, dim3((unsigned)grid), dim3((unsigned)threads), B.lds_bytes, st,
+                       (const Inst *)g_ws.insts, g_ws.ctl, g_ws.run, (int)B.lds_words);
     BT(hipGetLastError());
   } else {
-    // one iteration captured as a graph, replayed
-    hipStream_t cap;
-    BT(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-    {
-      std::lock_guard<std::mutex> lk(g_capture_mu);
-      BT(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-      enqueue_batch_iteration(B, g_ws.insts, g_ws.amap, cap);
-      BT(hipStreamEndCapture(cap, &graph));
+    BT(hipMemcpyAsync(g_ws.insts, insts.data(), sizeof(Inst) * (size_t)count,
+                      hipMemcpyHostToDevice, st));
+    BT(hipMemcpyAsync(g_ws.amap, amap.data(), sizeof(int2) * (size_t)total,
+                      hipMemcpyHostToDevice, st));
+    BT(hipFuncSetAttribute((const void *)B.antk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           (int)B.lds_bytes));
+    if (iterations == 1) {
+      enqueue_batch_iteration(B, g_ws.insts, g_ws.amap, st);
+      BT(hipGetLastError());
+    } else {
+      // one iteration captured as a graph, replayed
+      hipStream_t cap;
+      BT(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t graph;
+      hipGraphExec_t exec;
+      {
+        std::lock_guard<std::mutex> clk(g_capture_mu);
+        BT(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        enqueue_batch_iteration(B, g_ws.insts, g_ws.amap, cap);
+        BT(hipStreamEndCapture(cap, &graph));
+      }
+      BT(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      for (int32_t it = 0; it < iterations; ++it) BT(hipGraphLaunch(exec, st));
+      BT(hipGraphExecDestroy(exec));
+      BT(hipGraphDestroy(graph));
+      BT(hipStreamDestroy(cap));
     }
-    BT(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    for (int32_t it = 0; it < iterations; ++it) BT(hipGraphLaunch(exec, st));
-    BT(hipGraphExecDestroy(exec));
-    BT(hipGraphDestroy(graph));
-    BT(hipStreamDestroy(cap));
   }
   // later calls on each handle's stream, and the next batch, come after this one
   BT(hipEventRecord(g_ws.last_done, st));
   for (int32_t i = 0; i < count; ++i)
     if (hs[i]->stream != st) BT(hipStreamWaitEvent(hs[i]->stream, g_ws.last_done, 0));
 #undef BT
+  return FACO_OK;
+}
+
+// A second stream per batch stream, for the large instances of a split batch.
+struct SplitStream {
+  hipStream_t s = nullptr;
+  hipEvent_t start = nullptr, done = nullptr;
+};
+static std::map<hipStream_t, SplitStream> g_split_map;
+
+// One batch call with an explicit configuration: the whole batch at once, or
+// (big_percent > 0) the largest instances as a sub-batch of their own (waves
+// per ant big_team_waves) on a second stream beside the rest, the call still
+// ordered on st.
+static int run_batch_cfg(faco_instance *const *hs, int32_t count, int32_t iterations,
+                         hipStream_t st, const faco_batch_config &cfg) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  const int nbig = cfg.big_percent > 0 ? (count * cfg.big_percent + 99) / 100 : 0;
+  if (nbig == 0 || nbig >= count) return run_batch_one(hs, count, iterations, st, cfg);
+  hipError_t e;
+#define BT(expr)                                                                      \
+  if ((e = (expr)) != hipSuccess)                                                     \
+    return set_err(nullptr, FACO_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e));
+  std::vector<faco_instance *> order(hs, hs + count);
+  std::stable_sort(order.begin(), order.end(),
+                   [](const faco_instance *a, const faco_instance *b) { return a->n > b->n; });
+  SplitStream &sp = g_split_map[st];
+  if (!sp.s) {
+    BT(hipStreamCreateWithFlags(&sp.s, hipStreamNonBlocking));
+    BT(hipEventCreateWithFlags(&sp.start, hipEventDisableTiming));
+    BT(hipEventCreateWithFlags(&sp.done, hipEventDisableTiming));
+  }
+  // the second stream starts after the work already on st and ends before
+  // anything enqueued on st later
+  BT(hipEventRecord(sp.start, st));
+  BT(hipStreamWaitEvent(sp.s, sp.start, 0));
+  faco_batch_config big = cfg;
+  big.persistent = 0;
+  big.team_waves = cfg.big_team_waves;
+  big.big_percent = 0;
+  faco_batch_config small = cfg;
+  small.big_percent = 0;
+  int rc = run_batch_one(order.data(), nbig, iterations, sp.s, big);
+  if (rc) return rc;
+  rc = run_batch_one(order.data() + nbig, count - nbig, iterations, st, small);
+  if (rc) return rc;
+  BT(hipEventRecord(sp.done, sp.s));
+  BT(hipStreamWaitEvent(st, sp.done, 0));
+  for (int32_t i = 0; i < nbig; ++i)
+    if (order[(size_t)i]->stream != st) BT(hipStreamWaitEvent(order[(size_t)i]->stream, sp.done, 0));
+#undef BT
+  return FACO_OK;
+}
+
+static faco_batch_config config_for(faco_instance *const *hs, int32_t count) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto it = g_tuned.find(size_class(hs, count));
+  return it != g_tuned.end() ? it->second : g_batch_cfg;
+}
+
+extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,
+                              void *hip_stream) {
+  if (const char *m = check_batch_args(hs, count, iterations))
+    return set_err(nullptr, FACO_EINVAL, m);
+  if (count == 0 || iterations == 0) return FACO_OK;
+  return run_batch_cfg(hs, count, iterations, (hipStream_t)hip_stream, config_for(hs, count));
+}
+
+extern "C" int faco_autotune_batch(faco_instance *const *hs, int32_t count,
+                                   int32_t trial_iterations, void *hip_stream,
+                                   faco_batch_config *best_out) {
+  if (const char *m = check_batch_args(hs, count, trial_iterations))
+    return set_err(nullptr, FACO_EINVAL, m);
+  if (count == 0 || trial_iterations < 1)
+    return set_err(nullptr, FACO_EINVAL, "need at least one handle and one trial iteration");
+  hipStream_t st = (hipStream_t)hip_stream;
+  // twins of the handles from their stored inputs: the handles themselves
+  // do not move
+  std::vector<faco_instance *> twins;
+  auto drop = [&]() {
+    for (faco_instance *t : twins) faco_destroy_instance(t);
+  };
+  for (int32_t i = 0; i < count; ++i) {
+    faco_instance *t = nullptr;
+    const int rc = faco_build_instance(hs[i]->xy_host.data(), hs[i]->n, &hs[i]->p, hip_stream, &t);
+    if (rc) {
+      drop();
+      return rc;
+    }
+    twins.push_back(t);
+  }
+  // per phase: waves per ant, ants per workgroup, queue capacity; persistent
+  // teams; the largest 15% or 30% split off with 4-wave teams
+  std::vector<faco_batch_config> cand;
+  for (int tw : {1, 4, 8})
+    for (int apb : {1, 2})
+      for (int cap : {0, 2048}) {
+        if (tw > 1 && apb > 1) continue;
+        cand.push_back({0, tw, apb, cap, 0, 0});
+      }
+  for (int tw : {4, 8}) cand.push_back({1, tw, 1, 2048, 0, 0});
+  if (count >= 4)
+    for (int pct : {15, 30}) cand.push_back({0, 1, 1, 2048, pct, 4});
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    drop();
+    return set_err(nullptr, FACO_EDEVICE, "hipEventCreate failed");
+  }
+  float best_ms = 0.0f;
+  faco_batch_config best = g_batch_cfg;
+  bool have = false;
+  int rc = FACO_OK;
+  for (const faco_batch_config &c : cand) {
+    if (hipEventRecord(e0, st) != hipSuccess) { rc = FACO_EDEVICE; break; }
+    rc = run_batch_cfg(twins.data(), count, trial_iterations, st, c);
+    if (rc) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = set_err(nullptr, FACO_EDEVICE, "timing a trial failed");
+      break;
+    }
+    if (!have || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+      have = true;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  drop();
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_tuned[size_class(hs, count)] = best;
+  }
+  if (best_out) *best_out = best;
   return FACO_OK;
 }
 
@@ -929,7 +1181,7 @@ extern "C" int faco_run_batch_noalloc(faco_instance *const *hs, int32_t count,
   int2 *d_amap = reinterpret_cast<int2 *>(base + kScratchInstBytes);
   std::lock_guard<std::mutex> lk(g_batch_mu);
   BatchShape B;
-  batch_shape(hs, count, g_na_insts, g_na_amap, B);
+  batch_shape(hs, count, g_na_insts, g_na_amap, g_batch_cfg, B);
   BT(hipMemcpyAsync(d_insts, g_na_insts, sizeof(Inst) * (size_t)count, hipMemcpyHostToDevice,
                     st));
   BT(hipMemcpyAsync(d_amap, g_na_amap, sizeof(int2) * (size_t)B.total, hipMemcpyHostToDevice,

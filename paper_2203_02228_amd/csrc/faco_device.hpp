@@ -32,6 +32,9 @@ enum : int32_t {
   FAULT_LENGTH = 2,
   // an ant's route is not a permutation (route and pos disagree)
   FAULT_PERMUTATION = 4,
+  // a persistent batched launch saw no progress for a long time and left
+  // before this instance completed its iterations
+  FAULT_BATCH_STALL = 8,
 };
 
 // Device view of one instance (kernel argument).  Layouts:
@@ -119,6 +122,19 @@ constexpr int kMaxOrSeg = 3;
 __device__ __forceinline__ size_t srow(int p, int s, int k) {
   return ((size_t)(p >> 6) * (size_t)k + (size_t)s) * 64u + (size_t)(p & 63);
 }
+
+// Control of a persistent batched launch: one BatchCtl per instance (the
+// ticket of the next ant task, ants of the current iteration done,
+// iterations completed in the launch, ants per iteration) and one BatchRun.
+struct BatchCtl {
+  int64_t ticket;
+  int32_t done, epoch, ants, pad;
+};
+struct BatchRun {
+  int32_t count, iterations;
+  int32_t finished;  // instances that completed all their iterations
+  int32_t progress;  // ant tasks completed (stall detection)
+};
 
 // Default capacity of the LDS part of an ant's work queue (listed cities).
 constexpr int kLdsRingMax = 16384;

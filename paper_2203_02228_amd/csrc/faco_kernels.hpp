@@ -8,6 +8,7 @@
 #pragma once
 #include "device_common.hpp"
 #include "faco_device.hpp"
+#include "faco_update.hpp"
 
 namespace faco {
 
@@ -86,6 +87,7 @@ struct TeamLds {
   int64_t part[kMaxTeam];        // window: per-wave sums of source edge costs
   int64_t ub[kMaxTeam];          // nearest: per-wave bounds
   int cities[kMaxTeam * kWave];  // sweep: the batch of cities to test
+  int disp[4];                   // persistent batches: the next task
 };
 template <int TW>
 constexpr int team_words() {
@@ -1870,6 +1872,205 @@ __global__ void __launch_bounds__(TW > 1 ? 64 * TW : 256)
   if (w >= total) return;
   const int2 m = amap[w];
   run_ant<KT, 1>(insts[m.x], m.y, 0, lds + (size_t)wave * (size_t)lds_words);
+}
+
+// ===================================================================== //
+// Persistent batched execution.  One launch runs `iterations` iterations of
+// every instance of a batch, and each instance advances on its own: the ants
+// of its next iteration become available as soon as its own update is done,
+// whatever the other instances are doing.  Per instance (BatchCtl):
+//   ticket  ant tasks handed out in this launch (iteration e + 1 of the
+//           launch owns tickets e A .. e A + A - 1)
+//   done    ants of the current iteration that have finished
+//   epoch   iterations completed (update included) in this launch
+// Workers (a workgroup of TW waves when TW > 1, else each wave) take an ant
+// task by compare-and-swap on a ticket of the current iteration, so no ant
+// of iteration e + 2 can start before the update of iteration e + 1 is
+// published.  The worker that finishes an instance's last ant runs the
+// instance's update (colony, source, pheromone: the same functions as the
+// per-phase kernels) and publishes the next epoch.  Workers leave once every
+// instance has completed; a worker that sees no ant finish anywhere for
+// kStallPolls polls records a stall fault in every unfinished instance and
+// leaves, so no wait is unbounded.
+// ===================================================================== //
+constexpr int kStallPolls = 1 << 21;  // ~7 s of polls without any ant finishing
+
+// An ant task of the current iteration of some instance, largest instances
+// first (the host orders the table by tour length, descending).  The whole
+// wave scans 64 instances at a time; the lanes of instances with tickets
+// left try them in order, one at a time.  Uniform result.
+FACO_DEV bool grab_task(BatchCtl *ctl, int count, int iters, int &inst, int &ant) {
+  const int lane = lane_id();
+  for (int base = 0; base < count; base += kWave) {
+    const int i = base + lane;
+    int e = 0;
+    int64_t A = 0, t = 0;
+    bool avail = false;
+    if (i < count) {
+      e = ld_agent(&ctl[i].epoch);
+      if (e < iters) {
+        A = ctl[i].ants;
+        t = ld_agent64(&ctl[i].ticket);
+        avail = t < ((int64_t)e + 1) * A;
+      }
+    }
+    uint64_t m = ballot(avail);
+    while (m) {
+      const int l = ctz64(m);
+      m &= m - 1;
+      int won = 0, a = 0;
+      if (lane == l) {
+        const int64_t lim = ((int64_t)e + 1) * A;
+        while (t < lim) {
+          const int64_t seen = cas_agent64(&ctl[i].ticket, t, t + 1);
+          if (seen == t) {
+            won = 1;
+            a = (int)(t - (int64_t)e * A);
+            break;
+          }
+          t = seen;
+        }
+      }
+      if (readlane_i(won, l)) {
+        inst = base + l;
+        ant = readlane_i(a, l);
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
+// After an ant: count it; true for the instance's last ant of the iteration.
+// One lane.
+FACO_DEV bool finish_ant(BatchCtl *ctl, BatchRun *run, int inst) {
+  fence_release_agent();
+  const int d = add_agent(&ctl[inst].done, 1) + 1;
+  add_agent(&run->progress, 1);
+  return d == ctl[inst].ants;
+}
+
+// After the update: publish the next epoch.  One lane.
+FACO_DEV void publish_epoch(BatchCtl *ctl, BatchRun *run, int inst, int iters) {
+  st_agent(&ctl[inst].done, 0);
+  fence_release_agent();
+  const int e = ld_agent(&ctl[inst].epoch) + 1;
+  st_agent(&ctl[inst].epoch, e);
+  if (e == iters) add_agent(&run->finished, 1);
+}
+
+// The update of one instance by the worker's NT threads (thread tid).
+template <int TW>
+FACO_DEV void worker_update(const Inst &I, int tid, int nt) {
+  if (tid < kWave) run_colony(I);
+  if (TW > 1) team_sync(); else wave_fence();
+  for (int i = tid; i < I.n; i += nt) run_source(I, i, 0);
+  if (TW > 1) team_sync(); else wave_fence();
+  const size_t slots = (size_t)I.n * (size_t)I.k;
+  for (size_t s = (size_t)tid; s < slots; s += (size_t)nt) run_pheromone(I, s, 0);
+  if (TW > 1) team_sync(); else wave_fence();
+}
+
+FACO_DEV void mark_stall(const Inst *insts, BatchCtl *ctl, int count, int iters) {
+  for (int i = 0; i < count; ++i)
+    if (ld_agent(&ctl[i].epoch) < iters) atomicOr(&insts[i].st->fault, FAULT_BATCH_STALL);
+}
+
+template <int KT, int TW>
+__global__ void __launch_bounds__(TW > 1 ? 64 * TW : 256)
+    ant_persist_kernel(const Inst *insts, BatchCtl *ctl, BatchRun *run, int lds_words) {
+  extern __shared__ uint32_t lds[];
+  const int count = run->count, iters = run->iterations;
+  const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+  int polls = 0, seen = -1;
+  if (TW > 1) {
+    // the workgroup is one worker; wave 0 takes the tasks
+    TeamLds *tl = (TeamLds *)lds;
+    for (;;) {
+      if (w == 0) {
+        int cmd = 2, inst = 0, ant = 0;  // 0 ant, 1 idle, 2 leave, 3 stalled
+        if (uniform_i(ld_agent(&run->finished)) < count) {
+          if (grab_task(ctl, count, iters, inst, ant)) {
+            cmd = 0;
+          } else {
+            const int pr = uniform_i(ld_agent(&run->progress));
+            if (pr != seen) {
+              seen = pr;
+              polls = 0;
+            }
+            cmd = ++polls > kStallPolls ? 3 : 1;
+          }
+        }
+        if (lane == 0) {
+          tl->disp[0] = cmd;
+          tl->disp[1] = inst;
+          tl->disp[2] = ant;
+        }
+      }
+      team_sync();
+      const int cmd = uniform_i(tl->disp[0]);
+      const int inst = uniform_i(tl->disp[1]), ant = uniform_i(tl->disp[2]);
+      team_sync();  // every wave has read the task before it is replaced
+      if (cmd == 2) break;
+      if (cmd == 3) {
+        if (w == 0 && lane == 0) mark_stall(insts, ctl, count, iters);
+        break;
+      }
+      if (cmd == 1) {
+        __builtin_amdgcn_s_sleep(127);
+        continue;
+      }
+      fence_acquire_agent();
+      run_ant<KT, TW>(insts[inst], ant, 0, lds);
+      team_sync();
+      if (w == 0 && lane == 0) tl->disp[3] = finish_ant(ctl, run, inst) ? 1 : 0;
+      team_sync();
+      if (uniform_i(tl->disp[3])) {
+        fence_acquire_agent();
+        worker_update<TW>(insts[inst], (int)threadIdx.x, 64 * TW);
+        if (w == 0 && lane == 0) publish_epoch(ctl, run, inst, iters);
+      }
+    }
+  } else {
+    // every wave is a worker with its own slice of LDS
+    uint32_t *mine = lds + (size_t)w * (size_t)lds_words;
+    for (;;) {
+      int cmd = 2, inst = 0, ant = 0;  // 0 ant, 1 idle, 2 leave, 3 stalled
+      if (uniform_i(ld_agent(&run->finished)) < count) {
+        if (grab_task(ctl, count, iters, inst, ant)) {
+          cmd = 0;
+        } else {
+          const int pr = uniform_i(ld_agent(&run->progress));
+          if (pr != seen) {
+            seen = pr;
+            polls = 0;
+          }
+          cmd = ++polls > kStallPolls ? 3 : 1;
+        }
+      }
+      cmd = uniform_i(cmd);
+      inst = uniform_i(inst);
+      ant = uniform_i(ant);
+      if (cmd == 2) break;
+      if (cmd == 3) {
+        if (lane == 0) mark_stall(insts, ctl, count, iters);
+        break;
+      }
+      if (cmd == 1) {
+        __builtin_amdgcn_s_sleep(127);
+        continue;
+      }
+      fence_acquire_agent();
+      run_ant<KT, 1>(insts[inst], ant, 0, mine);
+      int last = 0;
+      if (lane == 0) last = finish_ant(ctl, run, inst) ? 1 : 0;
+      if (readlane_i(last, 0)) {
+        fence_acquire_agent();
+        worker_update<1>(insts[inst], lane, kWave);
+        if (lane == 0) publish_epoch(ctl, run, inst, iters);
+      }
+    }
+  }
 }
 
 }  // namespace faco

@@ -30,7 +30,8 @@ EXPORTED = ["faco_build_instance", "faco_run_iterations", "faco_get_best_tour",
             "faco_destroy_instance", "faco_last_error", "faco_run_batch",
             "faco_debug_get", "faco_footprint_bytes", "faco_set_timing",
             "faco_phase_times", "faco_set_batch_ants_per_block", "faco_set_team_waves",
-            "faco_set_queue_lds_capacity", "faco_set_verify", "faco_run_batch_noalloc"]
+            "faco_set_queue_lds_capacity", "faco_set_verify", "faco_run_batch_noalloc",
+            "faco_set_batch_config", "faco_get_batch_config", "faco_autotune_batch"]
 
 
 class faco_params(ctypes.Structure):
@@ -41,6 +42,15 @@ class faco_params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("ls_flags", ctypes.c_uint32),
                 ("oropt_max_seg", ctypes.c_int32), ("min_new_edges_max", ctypes.c_int32),
                 ("reserved1", ctypes.c_int32)]
+
+
+class faco_batch_config(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int32), ("team_waves", ctypes.c_int32),
+                ("ants_per_block", ctypes.c_int32), ("queue_lds_capacity", ctypes.c_int32),
+                ("big_percent", ctypes.c_int32), ("big_team_waves", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class FacoError(RuntimeError):
@@ -80,6 +90,13 @@ def lib():
         L.faco_last_error.argtypes = [vp]
         L.faco_run_batch.restype = ctypes.c_int
         L.faco_run_batch.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int32, vp]
+        L.faco_set_batch_config.restype = ctypes.c_int
+        L.faco_set_batch_config.argtypes = [P(faco_batch_config)]
+        L.faco_get_batch_config.restype = ctypes.c_int
+        L.faco_get_batch_config.argtypes = [P(faco_batch_config)]
+        L.faco_autotune_batch.restype = ctypes.c_int
+        L.faco_autotune_batch.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int32, vp,
+                                          P(faco_batch_config)]
         L.faco_run_batch_noalloc.restype = ctypes.c_int
         L.faco_run_batch_noalloc.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int32, vp]
         L.faco_debug_get.restype = ctypes.c_int
@@ -187,6 +204,30 @@ def faco_run_batch_noalloc(insts, iterations, stream=None):
     arr = (ctypes.c_void_p * len(insts))(*[i.h for i in insts])
     rc = lib().faco_run_batch_noalloc(arr, len(insts), int(iterations), _stream_handle(stream))
     _check(rc)
+
+
+def faco_set_batch_config(persistent=0, team_waves=0, ants_per_block=1,
+                          queue_lds_capacity=0, big_percent=0, big_team_waves=0):
+    c = faco_batch_config(persistent, team_waves, ants_per_block, queue_lds_capacity,
+                          big_percent, big_team_waves)
+    _check(lib().faco_set_batch_config(ctypes.byref(c)))
+
+
+def faco_get_batch_config():
+    c = faco_batch_config()
+    _check(lib().faco_get_batch_config(ctypes.byref(c)))
+    return c.as_dict()
+
+
+def faco_autotune_batch(insts, trial_iterations=5, stream=None):
+    """Time the candidate batch configurations on twins of `insts`, store
+    the fastest for their size class and return it (a dict)."""
+    arr = (ctypes.c_void_p * len(insts))(*[i.h for i in insts])
+    c = faco_batch_config()
+    rc = lib().faco_autotune_batch(arr, len(insts), int(trial_iterations),
+                                   _stream_handle(stream), ctypes.byref(c))
+    _check(rc)
+    return c.as_dict()
 
 
 def faco_set_batch_ants_per_block(apb):

@@ -56,10 +56,14 @@ def test_checker_accepts_uniform_barrier(tmp_path):
     assert st["barriers"] == 1 and bad == []
 
 
-def test_team_barriers_in_uniform_control_flow(tmp_path):
+@pytest.mark.parametrize("inst", [
+    "template __global__ void faco::ant_kernel<16, 8>(faco::Inst, int);",
+    # the persistent batched kernel: dispatch loop, ant, update, all on barriers
+    "template __global__ void faco::ant_persist_kernel<16, 8>(const faco::Inst *, "
+    "faco::BatchCtl *, faco::BatchRun *, int);",
+])
+def test_team_barriers_in_uniform_control_flow(tmp_path, inst):
     kern = os.path.join(ROOT, "paper_2203_02228_amd", "csrc", "faco_kernels.hpp")
-    st, bad = _uniformity(f'#include "{kern}"\n'
-                          "template __global__ void faco::ant_kernel<16, 8>(faco::Inst, int);\n",
-                          tmp_path)
+    st, bad = _uniformity(f'#include "{kern}"\n{inst}\n', tmp_path)
     assert st["barriers"] >= 20, st
     assert bad == [], f"barriers under divergent branches: {bad[:4]}"

@@ -38,37 +38,42 @@ def _batch_workloads(count):
     return ws
 
 
+@pytest.fixture
+def batch_config():
+    yield
+    F.faco_set_batch_config()   # back to the default
+
+
+@pytest.mark.parametrize("persistent", [1, 0])
 @pytest.mark.parametrize("apb", [1, 2, 4])
-def test_batch_equals_solo(apb):
+def test_batch_equals_solo(batch_config, persistent, apb):
     ws = _batch_workloads(10)
-    say(f"[gpu] batch apb={apb} sizes={[w.n for w in ws]}")
-    F.faco_set_batch_ants_per_block(apb)
+    say(f"[gpu] batch persistent={persistent} apb={apb} sizes={[w.n for w in ws]}")
+    F.faco_set_batch_config(persistent=persistent, team_waves=1, ants_per_block=apb)
     batch = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
     solo = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
-    F.faco_run_batch(batch, 1)      # direct launches
-    F.faco_run_batch(batch, 4)      # one captured iteration replayed 4 times
+    F.faco_run_batch(batch, 1)      # one iteration
+    F.faco_run_batch(batch, 4)      # persistent: one launch; else a replayed graph
     for g in solo:
         F.faco_run_iterations(g, 5)
     for w, gb, gs in zip(ws, batch, solo):
         assert _same(_state(gb), _state(gs)), w.name
-    F.faco_set_batch_ants_per_block(1)
+        assert F.faco_debug_get(gb, F.FACO_DBG_FAULT)[0] == 0
     for g in batch + solo:
         g.close()
 
 
+@pytest.mark.parametrize("persistent", [1, 0])
 @pytest.mark.parametrize("tw", [4, 8])
-def test_team_batch_equals_solo(tw):
+def test_team_batch_equals_solo(batch_config, persistent, tw):
     """Batched launches with a workgroup of tw waves per ant, on instances
     long enough for team rewrites."""
     ws = I.batch_instances(count=4, seed0=4100, n_lo=2500, n_hi=7000)
-    say(f"[gpu] team batch tw={tw} sizes={[w.n for w in ws]}")
-    F.faco_set_team_waves(tw)
-    try:
-        batch = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
-        F.faco_run_batch(batch, 1)
-        F.faco_run_batch(batch, 3)
-    finally:
-        F.faco_set_team_waves(0)
+    say(f"[gpu] team batch persistent={persistent} tw={tw} sizes={[w.n for w in ws]}")
+    F.faco_set_batch_config(persistent=persistent, team_waves=tw)
+    batch = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    F.faco_run_batch(batch, 1)
+    F.faco_run_batch(batch, 3)
     solo = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
     for g in solo:
         F.faco_run_iterations(g, 4)
@@ -93,6 +98,82 @@ def test_batch_matches_oracle():
         assert L == ol and np.array_equal(t, ot)
     for g in batch:
         g.close()
+
+
+def test_persistent_uneven_batch_many_workers_per_instance(batch_config):
+    """A persistent launch over instances of very different sizes and ant
+    counts (more ants than resident workers, instances finishing far apart):
+    each instance ends exactly where its solo run does, against the oracle."""
+    ws = I.batch_instances(count=24, seed0=4800, n_lo=60, n_hi=4000)
+    for i, w in enumerate(ws):
+        w.n_ants = [3, 16, 40, 9][i % 4]
+    say(f"[gpu] persistent uneven sizes={[w.n for w in ws]}")
+    F.faco_set_batch_config(persistent=1, team_waves=1, ants_per_block=4)
+    batch = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    F.faco_run_batch(batch, 7)
+    for w, g in list(zip(ws, batch))[::5]:
+        o = O.Oracle(w.points(), threads=8, **w.params())
+        o.run(7)
+        assert np.array_equal(F.faco_debug_get(g, F.FACO_DBG_ANT_ROUTES), o.ant_routes()), w.name
+        assert np.array_equal(F.faco_debug_get(g, F.FACO_DBG_PHEROMONE), o.pheromone()), w.name
+        assert F.faco_get_best_tour(g)[1] == o.best()[1]
+    for g in batch:
+        assert F.faco_debug_get(g, F.FACO_DBG_FAULT)[0] == 0
+        assert F.faco_debug_get(g, F.FACO_DBG_INFO)[0] == 7
+        g.close()
+
+
+def test_autotuner_leaves_handles_and_results_alone(batch_config):
+    ws = _batch_workloads(6)
+    say(f"[gpu] autotune sizes={[w.n for w in ws]}")
+    hs = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    before = [_state(g) for g in hs]
+    best = F.faco_autotune_batch(hs, trial_iterations=2)
+    assert best["persistent"] in (0, 1) and best["team_waves"] in (1, 4, 8)
+    assert best["ants_per_block"] in (1, 2, 4) and best["queue_lds_capacity"] in (0, 2048)
+    assert best["big_percent"] in (0, 15, 30)
+    for b, g in zip(before, hs):
+        assert _same(b, _state(g))          # tuning ran on twins
+        assert F.faco_debug_get(g, F.FACO_DBG_INFO)[0] == 0
+    F.faco_run_batch(hs, 3)                 # uses the stored configuration
+    solo = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    for g in solo:
+        F.faco_run_iterations(g, 3)
+    for w, gb, gs in zip(ws, hs, solo):
+        assert _same(_state(gb), _state(gs)), w.name
+    for g in hs + solo:
+        g.close()
+
+
+@pytest.mark.parametrize("pct,btw", [(25, 4), (50, 8), (10, 1)])
+def test_split_batch_equals_solo(batch_config, pct, btw):
+    """The longest tours split off as a sub-batch on a second stream: every
+    instance ends where its solo run does, and later work on the call's
+    stream sees the results."""
+    ws = I.batch_instances(count=9, seed0=4900, n_lo=300, n_hi=4500)
+    say(f"[gpu] split pct={pct} big tw={btw} sizes={[w.n for w in ws]}")
+    F.faco_set_batch_config(team_waves=1, queue_lds_capacity=2048, big_percent=pct,
+                            big_team_waves=btw)
+    batch = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    F.faco_run_batch(batch, 1)
+    F.faco_run_batch(batch, 4)
+    F.faco_run_iterations(batch[0], 1)        # on the call's stream, after it
+    solo = [F.faco_build_instance(w.points(), **w.params()) for w in ws]
+    for i, g in enumerate(solo):
+        F.faco_run_iterations(g, 6 if i == 0 else 5)
+    for w, gb, gs in zip(ws, batch, solo):
+        assert _same(_state(gb), _state(gs)), w.name
+    for g in batch + solo:
+        g.close()
+
+
+def test_batch_config_errors(batch_config):
+    for bad in [dict(persistent=2), dict(team_waves=3), dict(ants_per_block=3),
+                dict(queue_lds_capacity=10), dict(big_percent=101),
+                dict(big_percent=20, big_team_waves=2)]:
+        with pytest.raises(F.FacoError) as e:
+            F.faco_set_batch_config(**bad)
+        assert e.value.code == F.FACO_EINVAL
 
 
 def test_batch_rejects_bad_input():
