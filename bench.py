@@ -248,6 +248,18 @@ def run_served_mode(args):
     log(f"served: {count} request point sets in {time.time() - t0:.0f} s")
     torch.cuda.set_device(0)
     srv = S.Server(hbm_budget_bytes=args.hbm_budget << 30, chunk=args.chunk)
+    tuned, tune_s = {}, 0.0
+    if args.serve_tune:
+        # before the stream: a few requests of each size class, built aside
+        t0 = time.perf_counter()
+        per_class = {}
+        for (_, w), p in zip(reqs, pts):
+            c = srv._class_of(w.n)
+            if len(per_class.setdefault(c, [])) < 3:
+                per_class[c].append((p, w.params()))
+        tuned = srv.tune([x for v in per_class.values() for x in v])
+        tune_s = time.perf_counter() - t0
+        log(f"served: per-class autotune ({tune_s:.1f} s) -> {tuned}")
     t0 = time.perf_counter()
     futs = []
     for (arr, w), p in zip(reqs, pts):
@@ -261,6 +273,7 @@ def run_served_mode(args):
             log(f"served: {i + 1}/{count} results ({time.perf_counter() - t0:.0f} s)")
     makespan = time.perf_counter() - t0
     srv.close()
+    F.faco_set_batch_config()   # forget the tuned choices
     done = sorted(srv.completed, key=lambda r: r.rid)
     lat = S.latency_stats(done)
     lengths = {r.rid: r.result[1] for r in done}
@@ -306,6 +319,7 @@ def run_served_mode(args):
         "n_range": [min(w.n for _, w in reqs), max(w.n for _, w in reqs)],
         "errors": len(srv.errors),
         "latency_stages_s": stages,
+        "tuned_by_class": {str(k): v for k, v in tuned.items()}, "autotune_s": round(tune_s, 1),
     }
 
 
@@ -371,6 +385,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB for resident solves")
     ap.add_argument("--seq-sample", type=int, default=16)
+    ap.add_argument("--serve-tune", type=int, default=1)
     ap.add_argument("--result-timeout", type=float, default=900.0)
     ap.add_argument("--team-waves", type=int, default=0,
                     help="waves per ant (0 = the library's choice by size; 1, 4, 8)")

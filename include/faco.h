@@ -189,10 +189,10 @@ int faco_get_batch_config(faco_batch_config *config);
  * per workgroup for one-wave ants, LDS queue capacity as built or 2048;
  * persistent with 4/8-wave teams; the largest 15% or 30% of the instances
  * split off with 4-wave teams) on twins of the handles built from their own
- * inputs (the handles do not advance), keeps the fastest, and stores it for the batch's size class
- * (the longest tour's power of two): later faco_run_batch calls whose
- * longest tour falls in the same class use it.  best_out (may be NULL)
- * receives it.  Synchronises hip_stream.
+ * inputs (the handles do not advance), keeps the fastest, and stores it
+ * for the batch's size class (the longest tour's power of two): later
+ * faco_run_batch calls use the stored configuration of their own class,
+ * else of the nearest stored one.  best_out (may be NULL) receives it.  Synchronises hip_stream.
  * Errors: FACO_EINVAL, FACO_ENOMEM, FACO_EDEVICE. */
 int faco_autotune_batch(faco_instance *const *hs, int32_t count, int32_t trial_iterations,
                         void *hip_stream, faco_batch_config *best_out);

@@ -1020,10 +1020,16 @@ static int run_batch_cfg(faco_instance *const *hs, int32_t count, int32_t iterat
   return FACO_OK;
 }
 
+// The tuned configuration of the batch's size class, else of the nearest
+// tuned class (the smaller one on a tie), else the default.
 static faco_batch_config config_for(faco_instance *const *hs, int32_t count) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
-  auto it = g_tuned.find(size_class(hs, count));
-  return it != g_tuned.end() ? it->second : g_batch_cfg;
+  if (g_tuned.empty()) return g_batch_cfg;
+  const int c = size_class(hs, count);
+  int best = -1;
+  for (const auto &kv : g_tuned)
+    if (best < 0 || std::abs(kv.first - c) < std::abs(best - c)) best = kv.first;
+  return g_tuned[best];
 }
 
 extern "C" int faco_run_batch(faco_instance *const *hs, int32_t count, int32_t iterations,

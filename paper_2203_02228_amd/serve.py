@@ -58,6 +58,7 @@ class Server:
         self.closed = False
         self.completed = []
         self.errors = []
+        self.tuned = {}
         F.faco_set_batch_ants_per_block(ants_per_block)
         self.build_streams = [torch.cuda.Stream() for _ in range(builders)]
         self.run_streams = [torch.cuda.Stream() for _ in self.classes]
@@ -89,6 +90,26 @@ class Server:
             self._admit_locked()
             self.lock.notify_all()
         return r.future
+
+    def tune(self, samples, trial_iterations=3):
+        """Autotune the batch configuration of each size class on sample
+        requests [(xy, params)] built on the side (the library's autotuner
+        times every configuration on twins and stores the fastest for the
+        class; later batches of the class use it).  Returns {class: config}."""
+        by_class = {}
+        for xy, params in samples:
+            by_class.setdefault(self._class_of(len(xy)), []).append((xy, params))
+        out = {}
+        for c, items in sorted(by_class.items()):
+            stream = self.run_streams[c]
+            hs = [F.faco_build_instance(xy, stream=stream, **p) for xy, p in items]
+            try:
+                out[c] = F.faco_autotune_batch(hs, trial_iterations, stream=stream)
+            finally:
+                for h in hs:
+                    h.close()
+        self.tuned = out
+        return out
 
     def close(self, wait=True):
         with self.lock:
