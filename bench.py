@@ -450,9 +450,11 @@ def main():
     per = tk.mean(0) / args.steps
     tk_us = {name: round(float(per[i]) / 100.0, 1) for i, name in
              [(0, "construct"), (1, "ls_eval"), (2, "ls_apply"), (3, "sweep"), (4, "ant_total"),
-              (8, "spec_windows"), (9, "one_steps"), (10, "copies"), (11, "fallbacks")]}
+              (8, "spec_windows"), (9, "one_steps"), (10, "copies"), (11, "fallbacks"),
+              (13, "ls_eval_oropt"), (15, "ls_rewrite")]}
     tk_calls = {name: round(float(per[i]), 1) for i, name in
-                [(5, "spec_windows"), (6, "one_steps"), (7, "copies"), (12, "eval_rounds")]}
+                [(5, "spec_windows"), (6, "one_steps"), (7, "copies"), (12, "eval_rounds"),
+                 (14, "oropt_rounds")]}
     slowest_us = round(float(tk[:, 4].max()) / args.steps / 100.0, 1)
     dcnt = tot1 - tot0
     bytes_survey = float(survey_bytes_per_ant(dcnt, n, k).sum())

@@ -244,7 +244,10 @@ enum {
                                speculative windows, [9] one-step choices,
                                [10] copies, [11] backup/nearest choices; call
                                counts: [5] windows, [6] one-step choices, [7]
-                               copies, [12] evaluation rounds             */
+                               copies, [12] evaluation rounds, [13] ticks
+                               in Or-opt evaluation, [14] rounds that
+                               evaluated Or-opt, [15] ticks in the array
+                               rewrites of moves (part of [2])           */
   FACO_DBG_TEAM_WAVES = 13, /* int32 [1]: waves per ant of this instance   */
   FACO_DBG_FAULT = 14,      /* int64 [4]: FACO_FAULT_* bits found on the
                                device, the first fault's ant (-1: initial

@@ -76,7 +76,7 @@ FACO_DEV int wrap_off(int q, int off, int n) {
 constexpr int kMaxTeam = 8;
 enum TeamOp {
   OP_EXIT = 0, OP_REVERSE = 1, OP_SHIFT = 2, OP_WINDOW = 3, OP_SWEEP = 4, OP_COPY = 5,
-  OP_NEAREST = 6
+  OP_NEAREST = 6, OP_OROPT = 7
 };
 struct TeamLds {
   int op;
@@ -88,6 +88,8 @@ struct TeamLds {
   int64_t ub[kMaxTeam];          // nearest: per-wave bounds
   int cities[kMaxTeam * kWave];  // sweep: the batch of cities to test
   int disp[4];                   // persistent batches: the next task
+  int64_t okey[kMaxTeam][4];     // Or-opt: per-wave maxima of each listed city
+  int orx[14][kWave];            // Or-opt: the leader's loaded neighbourhoods
 };
 template <int TW>
 constexpr int team_words() {
@@ -967,8 +969,10 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
 }
 
 // Or-opt keys for the cities of the groups with `want` set (the others get 0).
+// slot_mask selects the segment variants (slots) to evaluate.
 template <int GS>
-FACO_DEV void eval_group_oropt(const Inst &I, bool want, GroupEval &R) {
+FACO_DEV void eval_group_oropt(const Inst &I, bool want, GroupEval &R,
+                               uint32_t slot_mask = (1u << kOrSlots) - 1u) {
   const int n = I.n, K = I.k, lane = lane_id();
   const int s = lane & (GS - 1);
   const bool act = want && s < K;
@@ -984,7 +988,7 @@ FACO_DEV void eval_group_oropt(const Inst &I, bool want, GroupEval &R) {
   for (int vi = 0; vi < kOrSlots; ++vi) {
     int dir, L, lf, ll, lp, lq;
     or_slot_lanes(vi, dir, L, lf, ll, lp, lq);
-    if (L > Lmax) continue;
+    if (L > Lmax || !((slot_mask >> vi) & 1u)) continue;
     const int2 xf = grp_lane2<GS>(xnb, lf), xl = grp_lane2<GS>(xnb, ll);
     const int2 xo = dir == 0 ? xl : xf;
     const int fpos = dir == 0 ? pa : wrapn(pa - L + 1, n);
@@ -1579,6 +1583,62 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
   return pushed;
 }
 
+// The Or-opt evaluation of an LS round, shared by the helper waves of a team.
+// The leader has loaded the listed cities' neighbourhoods and evaluated the
+// 2-opt moves; when a city before the first one with a 2-opt move needs
+// Or-opt, it leaves what the evaluation needs in tl->orx (lane by lane) and
+// helper wave w (1 <= w < TW) takes segment variants w - 1, w - 1 + (TW - 1),
+// ... for the cities before arg[0], leaving each city's maximum key in
+// tl->okey[w].  Keys order variants as the sequential evaluation does, so the
+// maximum over the waves is the sequential evaluation's result.
+template <int TW>
+FACO_DEV uint32_t or_slot_mask(int w) {
+  uint32_t m = 0;
+  for (int vi = w - 1; vi >= 0 && vi < kOrSlots; vi += TW - 1) m |= 1u << vi;
+  return m;
+}
+
+FACO_DEV void or_share(TeamLds *tl, const GroupEval &R) {
+  const int l = lane_id();
+  tl->orx[0][l] = R.pa;
+  tl->orx[1][l] = R.pb;
+  tl->orx[2][l] = R.pbs;
+  tl->orx[3][l] = R.pbp;
+  tl->orx[4][l] = R.d_ab;
+  tl->orx[5][l] = R.d_bs;
+  tl->orx[6][l] = R.d_bp;
+  tl->orx[7][l] = R.uc;
+  tl->orx[8][l] = R.xnb.x;
+  tl->orx[9][l] = R.xnb.y;
+  tl->orx[10][l] = R.xbs.x;
+  tl->orx[11][l] = R.xbs.y;
+  tl->orx[12][l] = R.xbp.x;
+  tl->orx[13][l] = R.xbp.y;
+}
+
+template <int KT, int TW>
+FACO_DEV void oropt_part(const Inst &I, int w, TeamLds *tl) {
+  constexpr int GS = KT <= 16 ? 16 : 32;
+  const uint32_t mask = or_slot_mask<TW>(w);
+  if (!mask) return;
+  const int l = lane_id(), grp = l / GS;
+  const int j2 = team_arg(tl, 0);
+  GroupEval R;
+  R.pa = tl->orx[0][l];
+  R.pb = tl->orx[1][l];
+  R.pbs = tl->orx[2][l];
+  R.pbp = tl->orx[3][l];
+  R.d_ab = tl->orx[4][l];
+  R.d_bs = tl->orx[5][l];
+  R.d_bp = tl->orx[6][l];
+  R.uc = tl->orx[7][l];
+  R.xnb = make_int2(tl->orx[8][l], tl->orx[9][l]);
+  R.xbs = make_int2(tl->orx[10][l], tl->orx[11][l]);
+  R.xbp = make_int2(tl->orx[12][l], tl->orx[13][l]);
+  eval_group_oropt<GS>(I, grp < j2, R, mask);
+  if ((l & (GS - 1)) == 0) tl->okey[w][grp] = R.keyo;
+}
+
 // The first fault of the instance keeps its ant (-1: the initial solution)
 // and the iteration being built.
 FACO_DEV void record_fault(const Inst &I, int32_t bit, int ant) {
@@ -1638,8 +1698,29 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       // Or-opt is only tried where no 2-opt move exists, and only cities
       // before the first one with a 2-opt move can be the chosen one
       const uint64_t h2 = ballot((lane & (GS - 1)) == 0 && grp < gcount && R.key2 > 0);
-      const int j2 = h2 ? ctz64(h2) / GS : gcount;
-      if ((flags & LS_OROPT) && j2 > 0) eval_group_oropt<GS>(I, grp < j2, R);
+      const int j2 = uniform_i(h2 ? ctz64(h2) / GS : gcount);
+      if (TW > 1 && (flags & LS_OROPT) && j2 > 0) {
+        // the team's helpers evaluate the Or-opt variants from the leader's loads
+        const int64_t to = ticks();
+        or_share(tl, R);
+        team_post(tl, OP_OROPT, j2);
+        team_sync();
+        int64_t k = 0;
+#pragma unroll
+        for (int w = 1; w < TW; ++w)
+          if (or_slot_mask<TW>(w)) {
+            const int64_t kw = tl->okey[w][grp];
+            k = kw > k ? kw : k;
+          }
+        R.keyo = grp < j2 ? k : 0;
+        tk[14]++;
+        tk[13] += ticks() - to;
+      } else if ((flags & LS_OROPT) && j2 > 0) {
+        const int64_t to = ticks();
+        eval_group_oropt<GS>(I, grp < j2, R);
+        tk[13] += ticks() - to;
+        tk[14]++;
+      }
       const int64_t t1 = ticks();
       tk[1] += t1 - t0;
       tk[12]++;
@@ -1658,9 +1739,11 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       cnt[CNT_LS_POPS] += npop;
       if (j >= gcount) continue;
       const Move mv = extract_move<GS>(I, R, j);
+      const int64_t ta = ticks();
       if (uniform_i(mv.kind) == 1) {
         cnt[CNT_MOVED_ELEMS] += apply_2opt<TW>(n, uniform_i(mv.px), uniform_i(mv.py),
                                                uniform_i(mv.pz), tl, route, pos, rxy);
+        tk[15] += ticks() - ta;
         const int pc[4] = {mv.w, mv.x, mv.y, mv.z};
         push_all<4>(n, pc, Q, inq, touched);
         cnt[CNT_MOVES_2OPT]++;
@@ -1670,6 +1753,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                             uniform_i(mv.pb), uniform_i(mv.fpos), uniform_i(mv.pq),
                             uniform_i(mv.pp), mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2, tl,
                             route, pos, rxy);
+        tk[15] += ticks() - ta;
         const int pc[6] = {mv.p, mv.q, mv.b, mv.e, mv.f, mv.l};
         push_all<6>(n, pc, Q, inq, touched);
         cnt[CNT_MOVES_OROPT]++;
@@ -1733,6 +1817,8 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
     } else if (op == OP_SWEEP) {
       sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, ord, route,
                          pos, rxy);
+    } else if (op == OP_OROPT) {
+      oropt_part<KT, TW>(I, w, tl);
     }
     team_sync();
   }
