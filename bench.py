@@ -379,7 +379,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-iterations", type=int, default=0)
     ap.add_argument("--batch-seq-count", type=int, default=32)
-    ap.add_argument("--tune-iterations", type=int, default=10)
+    ap.add_argument("--tune-iterations", type=int, default=30)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--chunk", type=int, default=10)

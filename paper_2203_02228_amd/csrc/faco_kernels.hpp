@@ -15,6 +15,15 @@ namespace faco {
 // q mod n; the common cases (q within one period of [0, n)) avoid a division
 FACO_DEV int64_t ticks() { return (int64_t)wall_clock64(); }
 
+// Clock reads inside the local-search rounds and the construction steps (the
+// per-phase breakdown); each one waits for the wave's outstanding LDS and
+// scalar operations.  Building with FACO_FINE_TICKS=0 leaves only the
+// per-ant totals.
+#ifndef FACO_FINE_TICKS
+#define FACO_FINE_TICKS 1
+#endif
+FACO_DEV int64_t fine_ticks() { return FACO_FINE_TICKS ? ticks() : 0; }
+
 // Per-ant event counters and tick sums, one per lane (lane c holds entry c)
 // instead of one scalar register pair each: the local search needs the
 // scalar registers for its own state.  Updates take the first active lane's
@@ -773,17 +782,17 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
       step = uniform_u64(step);
       const int maxw = new_edges >= m ? 1 : TW * kWave;
       int v, dv = 0, pv = 0;
-      const int64_t c0 = ticks();
+      const int64_t c0 = fine_ticks();
       if (maxw == 1) {
         v = one_step(I, t, (uint64_t)ant, step, pu, vis, D, dv, pv);
         tk[6]++;
-        tk[9] += ticks() - c0;
+        tk[9] += fine_ticks() - c0;
       } else {
         // accepted steps follow the source: q_1..q_acc appended at k..k+acc-1
         const WinOut o = team_window<KT, TW>(I, t, (uint64_t)ant, step, u, pu, dir, k, maxw,
                                              tl, vis, route, pos, rxy, D);
         tk[5]++;
-        tk[8] += ticks() - c0;
+        tk[8] += fine_ticks() - c0;
         const int acc = uniform_i(o.acc);
         v = uniform_i(o.v);
         dv = uniform_i(o.dv);
@@ -803,11 +812,11 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
         pv = pu;
       } else {
         if (v == -1) {
-          const int64_t c1 = ticks();
+          const int64_t c1 = fine_ticks();
           v = uniform_i(select_fallback<TW>(I, u, vis, tl, cnt));
           dv = uniform_i(cost(I.xy[u], I.xy[v]));
           pv = uniform_i(I.src_pos[v]);
-          tk[11] += ticks() - c1;
+          tk[11] += fine_ticks() - c1;
         }
         ++step;
         len += dv;
@@ -830,11 +839,11 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
       k = uniform_i(k);
       dir = uniform_i(dir);
       if (new_edges >= m && k < n) {
-        const int64_t c2 = ticks();
+        const int64_t c2 = fine_ticks();
         const int app = copy_from<TW>(I, pv, k, u, pu, len, tl, route, pos, rxy, vis);
         cnt[CNT_COPIED] += app;
         tk[7]++;
-        tk[10] += ticks() - c2;
+        tk[10] += fine_ticks() - c2;
       }
     }
   }
@@ -1693,7 +1702,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       int a = e[0];
 #pragma unroll
       for (int g = 1; g < G; ++g) a = grp == g ? e[g] : a;
-      const int64_t t0 = ticks();
+      const int64_t t0 = fine_ticks();
       GroupEval R = eval_group<GS>(I, flags, a, grp < gcount, route, pos, rxy);
       // Or-opt is only tried where no 2-opt move exists, and only cities
       // before the first one with a 2-opt move can be the chosen one
@@ -1701,7 +1710,7 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       const int j2 = uniform_i(h2 ? ctz64(h2) / GS : gcount);
       if (TW > 1 && (flags & LS_OROPT) && j2 > 0) {
         // the team's helpers evaluate the Or-opt variants from the leader's loads
-        const int64_t to = ticks();
+        const int64_t to = fine_ticks();
         or_share(tl, R);
         team_post(tl, OP_OROPT, j2);
         team_sync();
@@ -1714,14 +1723,14 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
           }
         R.keyo = grp < j2 ? k : 0;
         tk[14]++;
-        tk[13] += ticks() - to;
+        tk[13] += fine_ticks() - to;
       } else if ((flags & LS_OROPT) && j2 > 0) {
-        const int64_t to = ticks();
+        const int64_t to = fine_ticks();
         eval_group_oropt<GS>(I, grp < j2, R);
-        tk[13] += ticks() - to;
+        tk[13] += fine_ticks() - to;
         tk[14]++;
       }
-      const int64_t t1 = ticks();
+      const int64_t t1 = fine_ticks();
       tk[1] += t1 - t0;
       tk[12]++;
       const uint64_t hm = ballot((lane & (GS - 1)) == 0 && grp < gcount &&
@@ -1739,11 +1748,11 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       cnt[CNT_LS_POPS] += npop;
       if (j >= gcount) continue;
       const Move mv = extract_move<GS>(I, R, j);
-      const int64_t ta = ticks();
+      const int64_t ta = fine_ticks();
       if (uniform_i(mv.kind) == 1) {
         cnt[CNT_MOVED_ELEMS] += apply_2opt<TW>(n, uniform_i(mv.px), uniform_i(mv.py),
                                                uniform_i(mv.pz), tl, route, pos, rxy);
-        tk[15] += ticks() - ta;
+        tk[15] += fine_ticks() - ta;
         const int pc[4] = {mv.w, mv.x, mv.y, mv.z};
         push_all<4>(n, pc, Q, inq, touched);
         cnt[CNT_MOVES_2OPT]++;
@@ -1753,12 +1762,12 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                             uniform_i(mv.pb), uniform_i(mv.fpos), uniform_i(mv.pq),
                             uniform_i(mv.pp), mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2, tl,
                             route, pos, rxy);
-        tk[15] += ticks() - ta;
+        tk[15] += fine_ticks() - ta;
         const int pc[6] = {mv.p, mv.q, mv.b, mv.e, mv.f, mv.l};
         push_all<6>(n, pc, Q, inq, touched);
         cnt[CNT_MOVES_OROPT]++;
       }
-      tk[2] += ticks() - t1;
+      tk[2] += fine_ticks() - t1;
       ++changes;
       gain += mv.gain;
     }
