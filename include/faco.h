@@ -222,7 +222,7 @@ int faco_set_queue_lds_capacity(int32_t capacity);
  * then copy `bytes` bytes into the host buffer `out`; `bytes` must equal the
  * size given below, otherwise FACO_EINVAL. */
 enum {
-  FACO_DBG_ANT_ROUTES = 0,   /* int32 [n_ants][n]                            */
+  FACO_DBG_ANT_ROUTES = 0,   /* int32 [n_ants][n]; all -1 before iteration 1 */
   FACO_DBG_ANT_LENGTHS = 1,  /* int64 [n_ants]                               */
   FACO_DBG_PHEROMONE = 2,    /* float [n][k_eff]                             */
   FACO_DBG_SOURCE = 3,       /* int32 [n]                                    */
