@@ -218,6 +218,26 @@ int faco_set_team_waves(int32_t team_waves);
  * that never changes results.  Errors: FACO_EINVAL. */
 int faco_set_queue_lds_capacity(int32_t capacity);
 
+/* How the local search of faco_run_iterations holds each ant's tour, for
+ * instances built after the call (process-wide).  Sec. 4.4: a 2-opt flip on
+ * an array rewrites O(n) elements.  With segment lists the tour is the array
+ * of the last materialisation read through up to max_records records in LDS
+ * (a storage range, its orientation, the array position of its first
+ * element); a move splits at most three records and rewrites the records
+ * inside its range, and when the records run short the tour is written out
+ * in array order (materialised) and cut again into segments of
+ * 2^length_log2 cities.  Array positions, and so every rule that depends on
+ * them, are exactly those of the flat arrays: results never change.
+ *   mode: 0 (the default) or 1 flat arrays, 2 segment lists.
+ *   length_log2: 0 for the smallest power of two >= 64 that cuts the tour
+ *         into at most 512 segments, else 1..24.
+ *   max_records: 0 for 2048, else 8..2048; it must exceed the tour's
+ *         segment count by 4 (checked at build: FACO_EINVAL).
+ * Segment lists take 24 n bytes more per ant (a second array buffer and a
+ * record label per city).  faco_run_batch and the initial solution always
+ * use flat arrays.  Errors: FACO_EINVAL. */
+int faco_set_tour_segments(int32_t mode, int32_t length_log2, int32_t max_records);
+
 /* Debug / test dumps of the state after the last completed iteration.  Sync,
  * then copy `bytes` bytes into the host buffer `out`; `bytes` must equal the
  * size given below, otherwise FACO_EINVAL. */
@@ -237,7 +257,7 @@ enum {
   FACO_DBG_INIT_COUNTERS = 10, /* int64 [FACO_NCNT] of the initial solution  */
   FACO_DBG_COUNTER_TOTALS = 11, /* int64 [n_ants][FACO_NCNT], summed over all
                                    iterations since the build                 */
-  FACO_DBG_PHASE_TICKS = 12, /* int64 [n_ants][16] summed since the build;
+  FACO_DBG_PHASE_TICKS = 12, /* int64 [n_ants][24] summed since the build;
                                device wall-clock ticks (100 MHz): [0]
                                construction, [1] move evaluation, [2] move
                                application, [3] sweeps, [4] whole ant, [8]
@@ -247,13 +267,18 @@ enum {
                                copies, [12] evaluation rounds, [13] ticks
                                in Or-opt evaluation, [14] rounds that
                                evaluated Or-opt, [15] ticks in the array
-                               rewrites of moves (part of [2])           */
+                               rewrites of moves (part of [2]); segment
+                               lists: [16] materialisations, [17] ticks in
+                               them, [18] cities relabelled by splits, [19]
+                               splits, [20] records passed by moves, [21]
+                               ticks of the leader's part of moves, [22]
+                               ticks of the team's part; [23] zero        */
   FACO_DBG_TEAM_WAVES = 13, /* int32 [1]: waves per ant of this instance   */
   FACO_DBG_FAULT = 14,      /* int64 [4]: FACO_FAULT_* bits found on the
                                device, the first fault's ant (-1: initial
                                solution or global best) and iteration, and
                                the number of tours verified so far           */
-  FACO_DBG_RECOMPUTED_LENGTHS = 15 /* int64 [n_ants + 1]: runs the tour-length
+  FACO_DBG_RECOMPUTED_LENGTHS = 15, /* int64 [n_ants + 1]: runs the tour-length
                                verification now (Alg. 2's select_shortest
                                relies on the lengths) and returns every ant's
                                tour length recomputed from its stored route
@@ -262,6 +287,8 @@ enum {
                                0 for the ants before the first iteration.
                                A mismatch with the tracked lengths sets a
                                fault.                                         */
+  FACO_DBG_TOUR = 16        /* int64 [3]: segment lists in use (0/1), their
+                               segment length, the record limit              */
 };
 /* device faults (FACO_DBG_FAULT; faco_get_best_tour then returns
  * FACO_EDEVICE) */

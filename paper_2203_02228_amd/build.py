@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["faco_api.hip", "ant_tw1.hip", "ant_tw4.hip", "ant_tw8.hip",
-           "ant_ps1.hip", "ant_ps4.hip", "ant_ps8.hip"]
+           "ant_ps1.hip", "ant_ps4.hip", "ant_ps8.hip",
+           "ant_sg1.hip", "ant_sg4.hip", "ant_sg8.hip"]
 OUT = os.path.join(HERE, "libfaco_hip.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -20,3 +20,8 @@ AntBatchFn faco_ant_batch_kernel(int k, int tw);
 AntPersistFn faco_ant_persist_kernel(int k, int tw);
 // LDS words of the team area ahead of an ant's bitmaps
 int faco_team_lds_words(int tw);
+// ant kernel whose local search runs on segment-list tours (Inst.seg_on)
+AntKernelFn faco_ant_seg_kernel(int k, int tw);
+// LDS words ahead of the segment records of such a kernel (team area and the
+// three bitmaps, rounded up to 16 bytes)
+int faco_seg_lds_words(int tw, int n);

@@ -126,6 +126,14 @@ FACO_DEV uint64_t uniform_u64(uint64_t v) {
 // wave of the workgroup after it.
 FACO_DEV void team_sync() { __syncthreads(); }
 
+// Order this wave's LDS writes before its later LDS reads (a write by one
+// lane read back by all).
+FACO_DEV void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Make this wave's global and LDS writes visible to its other lanes.
 FACO_DEV void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

@@ -35,7 +35,8 @@ struct faco_instance {
   Inst dv{};
   std::vector<void *> allocs;
   std::string err;
-  size_t lds_ant = 0;
+  size_t lds_ant = 0;   // LDS of the per-iteration ant kernel
+  size_t lds_init = 0;  // LDS of the initial solution's ant kernel (flat tour)
   int tw = 1;  // waves per ant in the per-instance ant kernel
   int device = 0;  // the device current at build
   std::vector<int32_t> orig_of, int_of;  // internal label <-> original city number
@@ -94,26 +95,6 @@ static void effective_sizes(int32_t n, const faco_params *p, int32_t *k, int32_t
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
-  if (validate(p, n)) return 0;
-  int32_t k, bl;
-  effective_sizes(n, p, &k, &bl);
-  const uint64_t N = (uint64_t)n, A = (uint64_t)p->n_ants;
-  uint64_t b = 0;
-  b += align_up(8 * N);                    // xy
-  b += align_up(16 * ((N + 31) / 32));     // bounding boxes of 32-label words
-  const uint64_t NB = (N + 63) / 64 * 64;   // source-ordered tables: whole 64-position blocks
-  b += 4 * align_up(4 * N * (uint64_t)k);   // cl, cost, eta, tau
-  b += 4 * align_up(4 * NB * (uint64_t)k);  // source-ordered city, weight, position, cost
-  b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
-  b += 4 * align_up(4 * N) + 2 * align_up(8 * N); // source route/pos/edge costs/coordinates, adjacency, global best
-  b += 2 * align_up(4 * N);                   // label maps
-  b += 3 * align_up(4 * N * A) + align_up(8 * N * A);  // ant routes, pos, rings, tour coordinates
-  b += align_up(8 * A) + 2 * align_up(8 * A * faco::NCNT) + align_up(128 * A);
-  b += 2 * align_up(8 * (A + 1)) + align_up(4 * (A + 1));  // verification
-  b += align_up(sizeof(DevState));
-  return b;
-}
 
 // Held while a batch graph is being captured, and around device allocation
 // and release, which may synchronise implicitly and must not meet a capture
@@ -186,13 +167,14 @@ extern "C" int faco_set_queue_lds_capacity(int32_t cap) {
 
 // The queue ring takes what LDS is left next to the team area and three
 // n-bit bitmaps (160 KB per CU).
-static int queue_lds_cap_for(int32_t n) {
+static int queue_lds_cap_for(int32_t n, int extra_words = 0) {
   int cap;
   {
     std::lock_guard<std::mutex> lk(g_team_mu);
     cap = n < g_queue_lds_cap ? n : g_queue_lds_cap;
   }
-  const int room = 160 * 1024 / 4 - faco_team_lds_words(8) - 3 * ((n + 31) / 32);
+  const int room = 160 * 1024 / 4 - faco_team_lds_words(8) - 3 * ((n + 31) / 32) - 4 -
+                   extra_words;
   return cap < room ? cap : room;
 }
 
@@ -207,6 +189,88 @@ static int team_waves_for(int32_t n, int32_t ants) {
   if (ants <= 256) return 8;
   if (ants <= 512) return 4;
   return 1;
+}
+
+// Segment-list ant tours: 0 and 1 flat arrays (the default: on this GPU a
+// segment-list move costs as much as a flat rewrite of a typical move, and
+// every evaluation pays the record lookups), 2 segment lists; segment length
+// 2^g_seg_log2 (0: by size); records in use that trigger a materialisation
+// (0: the table's capacity).
+static int g_seg_mode = 0, g_seg_log2 = 0, g_seg_max = 0;
+
+extern "C" int faco_set_tour_segments(int32_t mode, int32_t length_log2,
+                                      int32_t max_records) {
+  if (mode < 0 || mode > 2)
+    return set_err(nullptr, FACO_EINVAL, "tour segment mode must be 0, 1 or 2");
+  if (length_log2 < 0 || length_log2 > 24)
+    return set_err(nullptr, FACO_EINVAL, "segment length log2 must be in [0, 24]");
+  if (max_records != 0 && (max_records < 8 || max_records > faco::kSegCap))
+    return set_err(nullptr, FACO_EINVAL, "segment records must be 0 or in [8, 2048]");
+  std::lock_guard<std::mutex> lk(g_team_mu);
+  g_seg_mode = mode;
+  g_seg_log2 = length_log2;
+  g_seg_max = max_records;
+  return FACO_OK;
+}
+
+struct SegPlan {
+  int on = 0, shift = 0, max = 0;
+};
+
+// Whether an instance of n cities whose ants have tw waves runs its local
+// search on segment lists, and with which segment length and record limit.
+// Auto length: the smallest power of two >= 64 that cuts the tour into at
+// most a quarter of the record table.
+static int seg_plan(int32_t n, int tw, SegPlan *sp) {
+  int mode, lg, mx;
+  {
+    std::lock_guard<std::mutex> lk(g_team_mu);
+    mode = g_seg_mode;
+    lg = g_seg_log2;
+    mx = g_seg_max;
+  }
+  *sp = SegPlan{};
+  (void)tw;
+  if (mode != 2) return FACO_OK;
+  sp->on = 1;
+  sp->max = mx ? mx : faco::kSegCap;
+  if (lg) {
+    sp->shift = lg;
+  } else {
+    sp->shift = 6;
+    while (((int64_t)n + (1 << sp->shift) - 1) >> sp->shift > faco::kSegCap / 4) ++sp->shift;
+  }
+  const int64_t chunks = ((int64_t)n + (1 << sp->shift) - 1) >> sp->shift;
+  if (chunks + 4 > sp->max)
+    return set_err(nullptr, FACO_EINVAL,
+                   "segment records must exceed the tour's chunks by 4 (raise the record "
+                   "limit or the segment length)");
+  return FACO_OK;
+}
+
+extern "C" uint64_t faco_footprint_bytes(int32_t n, const faco_params *p) {
+  if (validate(p, n)) return 0;
+  int32_t k, bl;
+  effective_sizes(n, p, &k, &bl);
+  const uint64_t N = (uint64_t)n, A = (uint64_t)p->n_ants;
+  uint64_t b = 0;
+  b += align_up(8 * N);                    // xy
+  b += align_up(16 * ((N + 31) / 32));     // bounding boxes of 32-label words
+  const uint64_t NB = (N + 63) / 64 * 64;   // source-ordered tables: whole 64-position blocks
+  b += 4 * align_up(4 * N * (uint64_t)k);   // cl, cost, eta, tau
+  b += 4 * align_up(4 * NB * (uint64_t)k);  // source-ordered city, weight, position, cost
+  b += align_up(4 * N * (uint64_t)bl + 4); // backup lists
+  b += 4 * align_up(4 * N) + 2 * align_up(8 * N); // source route/pos/edge costs/coordinates, adjacency, global best
+  b += 2 * align_up(4 * N);                   // label maps
+  b += 3 * align_up(4 * N * A) + align_up(8 * N * A);  // ant routes, pos, rings, tour coordinates
+  b += align_up(8 * A) + 2 * align_up(8 * A * faco::NCNT) + align_up(8 * faco::kTicks * A);
+  b += align_up(4 * A);  // final tour buffer of each ant
+  SegPlan sp;
+  if (seg_plan(n, team_waves_for(n, p->n_ants), &sp) == FACO_OK && sp.on)
+    b += 2 * align_up(4 * N * A) + 2 * align_up(8 * N * A) + align_up(4 * A);  // segment lists
+  b += 2 * align_up(8 * (A + 1)) + align_up(4 * (A + 1));  // verification
+  b += align_up(sizeof(DevState));
+  return b;
 }
 
 // tour-length verification of the ants (ants != 0) and the global best
@@ -227,8 +291,8 @@ static int enqueue_iteration(faco_instance *h) {
   const unsigned nb_tau = (unsigned)((slots + 255) / 256);
   TimedLaunch tl;
   if (h->timing) begin_timed(h, 0, tl);
-  hipLaunchKernelGGL(faco_ant_kernel(h->k, h->tw), dim3(h->p.n_ants), dim3(64 * h->tw),
-                     h->lds_ant, h->stream, I, 0);
+  hipLaunchKernelGGL(I.seg_on ? faco_ant_seg_kernel(h->k, h->tw) : faco_ant_kernel(h->k, h->tw),
+                     dim3(h->p.n_ants), dim3(64 * h->tw), h->lds_ant, h->stream, I, 0);
   if (h->timing) {
     end_timed(h, tl);
     begin_timed(h, 1, tl);
@@ -307,8 +371,12 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   for (int64_t i = 0; i < 2 * (int64_t)n; ++i)
     if (xy[i] < 0 || xy[i] >= (1 << 26))
       return set_err(nullptr, FACO_EINVAL, "coordinates must be in [0, 2^26)");
+  const int tw = team_waves_for(n, p->n_ants);
+  SegPlan sp;
+  if (int rc = seg_plan(n, tw, &sp)) return rc;
 
   faco_instance *h = new faco_instance();
+  h->tw = tw;
   h->p = *p;
   h->n = n;
   h->xy_host.assign(xy, xy + 2 * (size_t)n);
@@ -329,7 +397,10 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   I.m = p->min_new_edges;
   I.m_hi = p->min_new_edges_max;
   I.verify = 0;
-  I.lcap = queue_lds_cap_for(n);
+  I.seg_on = sp.on;
+  I.seg_shift = sp.shift;
+  I.seg_max = sp.max;
+  I.lcap = queue_lds_cap_for(n, sp.on ? 4 * sp.max : 0);
   I.rho = p->rho;
   I.ls_flags = p->ls_flags;
   I.oropt_max = p->oropt_max_seg;
@@ -372,7 +443,15 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   ALLOC(lens, int64_t, A);
   ALLOC(cnt, int64_t, A * faco::NCNT);
   ALLOC(cnt_acc, int64_t, A * faco::NCNT);
-  ALLOC(ticks, int64_t, A * 16);
+  ALLOC(ticks, int64_t, A * faco::kTicks);
+  ALLOC(rsel, int32_t, A);
+  if (sp.on) {
+    ALLOC(r2, int32_t, N * A);
+    ALLOC(p2, int32_t, N * A);
+    ALLOC(x2, int2, N * A);
+    ALLOC(sgid, int2, N * A);
+    ALLOC(sepoch, int32_t, A);
+  }
   ALLOC(vsum, int64_t, A + 1);
   ALLOC(vbad, int32_t, A + 1);
   ALLOC(vout, int64_t, A + 1);
@@ -397,7 +476,13 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   BTRY(hipMemsetAsync(I.routes, 0xFF, sizeof(int32_t) * N * A, h->stream));
   BTRY(hipMemsetAsync(I.lens, 0, sizeof(int64_t) * A, h->stream));
   BTRY(hipMemsetAsync(I.cnt, 0, sizeof(int64_t) * A * faco::NCNT, h->stream));
-  BTRY(hipMemsetAsync(I.ticks, 0, sizeof(int64_t) * A * 16, h->stream));
+  BTRY(hipMemsetAsync(I.ticks, 0, sizeof(int64_t) * A * faco::kTicks, h->stream));
+  BTRY(hipMemsetAsync(I.rsel, 0, sizeof(int32_t) * A, h->stream));
+  if (sp.on) {
+    // epochs start at 1: no record label matches before it is written
+    BTRY(hipMemsetAsync(I.sgid, 0, sizeof(int2) * N * A, h->stream));
+    BTRY(hipMemsetAsync(I.sepoch, 0, sizeof(int32_t) * A, h->stream));
+  }
   BTRY(hipMemsetAsync(I.vsum, 0, sizeof(int64_t) * (A + 1), h->stream));
   BTRY(hipMemsetAsync(I.vbad, 0, sizeof(int32_t) * (A + 1), h->stream));
   BTRY(hipMemsetAsync(I.vout, 0, sizeof(int64_t) * (A + 1), h->stream));
@@ -448,13 +533,20 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
     return fail(FACO_EDUP);
   }
 
-  h->tw = team_waves_for(n, p->n_ants);
-  h->lds_ant = sizeof(uint32_t) * ((size_t)faco_team_lds_words(h->tw) +
-                                   3 * (size_t)((n + 31) / 32) + (size_t)I.lcap);
+  h->lds_init = sizeof(uint32_t) * ((size_t)faco_team_lds_words(h->tw) +
+                                    3 * (size_t)((n + 31) / 32) + (size_t)I.lcap);
   BTRY(hipFuncSetAttribute((const void *)faco_ant_kernel(h->k, h->tw),
-                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_ant));
-  // initial solution (ant slot 0), limits, tau = tau_max, source = global best
-  hipLaunchKernelGGL(faco_ant_kernel(h->k, h->tw), dim3(1), dim3(64 * h->tw), h->lds_ant,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_init));
+  h->lds_ant = h->lds_init;
+  if (I.seg_on) {
+    h->lds_ant = sizeof(uint32_t) * ((size_t)faco_seg_lds_words(h->tw, n) +
+                                     4 * (size_t)I.seg_max + (size_t)I.lcap);
+    BTRY(hipFuncSetAttribute((const void *)faco_ant_seg_kernel(h->k, h->tw),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_ant));
+  }
+  // initial solution (ant slot 0, flat tour), limits, tau = tau_max, source =
+  // global best
+  hipLaunchKernelGGL(faco_ant_kernel(h->k, h->tw), dim3(1), dim3(64 * h->tw), h->lds_init,
                      h->stream, I, 1);
   if (p->ls_flags & FACO_LS_INIT_3OPT) {
     // the initial search with 3-opt, on the nearest-neighbour tour
@@ -557,13 +649,23 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
   DevState hs;
   HIP_TRY(h, d2h(h, &hs, h->dv.st, sizeof(DevState)));
   switch (what) {
-    case FACO_DBG_ANT_ROUTES: src = h->dv.routes; need = 4 * N * A; break;
+    case FACO_DBG_ANT_ROUTES: {
+      // each ant's tour sits in the storage buffer its local search left it in
+      if (bytes != 4 * N * A) return set_err(h, FACO_EINVAL, "size mismatch");
+      std::vector<int32_t> sel(A);
+      HIP_TRY(h, d2h(h, sel.data(), h->dv.rsel, 4 * A));
+      for (size_t a = 0; a < A; ++a) {
+        const int32_t *base = sel[a] && h->dv.r2 ? h->dv.r2 : h->dv.routes;
+        HIP_TRY(h, d2h(h, (int32_t *)out + a * N, base + a * N, 4 * N));
+      }
+      break;
+    }
     case FACO_DBG_ANT_LENGTHS: src = h->dv.lens; need = 8 * A; break;
     case FACO_DBG_PHEROMONE: src = h->dv.tau; need = 4 * N * K; break;
     case FACO_DBG_SOURCE: src = h->dv.src_route; need = 4 * N; break;
     case FACO_DBG_COUNTERS: src = h->dv.cnt; need = 8 * A * faco::NCNT; break;
     case FACO_DBG_COUNTER_TOTALS: src = h->dv.cnt_acc; need = 8 * A * faco::NCNT; break;
-    case FACO_DBG_PHASE_TICKS: src = h->dv.ticks; need = 8 * A * 16; break;
+    case FACO_DBG_PHASE_TICKS: src = h->dv.ticks; need = 8 * A * faco::kTicks; break;
     case FACO_DBG_CAND_LISTS: src = h->dv.cl; need = 4 * N * K; break;
     case FACO_DBG_BACKUP_LISTS: src = h->dv.bll; need = 4 * N * BL; break;
     case FACO_DBG_HEURISTIC: src = h->dv.eta; need = 4 * N * K; break;
@@ -601,6 +703,13 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
       std::memcpy(out, &tw, 4);
       return FACO_OK;
     }
+    case FACO_DBG_TOUR: {
+      if (bytes != 24) return set_err(h, FACO_EINVAL, "size mismatch");
+      const Inst &I = h->dv;
+      int64_t v[3] = {I.seg_on, I.seg_on ? (int64_t)1 << I.seg_shift : 0, I.seg_max};
+      std::memcpy(out, v, 24);
+      return FACO_OK;
+    }
     case FACO_DBG_INIT_COUNTERS: {
       if (bytes != 8 * faco::NCNT) return set_err(h, FACO_EINVAL, "size mismatch");
       std::memcpy(out, hs.init_cnt, 8 * faco::NCNT);
@@ -608,8 +717,10 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
     }
     default: return set_err(h, FACO_EINVAL, "unknown dump");
   }
-  if (bytes != need) return set_err(h, FACO_EINVAL, "size mismatch");
-  if (need) HIP_TRY(h, d2h(h, out, src, need));
+  if (what != FACO_DBG_ANT_ROUTES) {
+    if (bytes != need) return set_err(h, FACO_EINVAL, "size mismatch");
+    if (need) HIP_TRY(h, d2h(h, out, src, need));
+  }
   // back to original city numbers: city values, and rows indexed by city
   const auto &orig = h->orig_of;
   auto map_values = [&](int32_t *v, size_t cnt) {

@@ -50,8 +50,8 @@ FACO_DEV void verify_part(const Inst &I, int tour, int ants, int chunk, int nchu
   const int n = I.n;
   const bool gb = tour == I.A;
   if (!gb && !ants) return;
-  const int32_t *r = gb ? I.gb_route : I.routes + (size_t)tour * (size_t)n;
-  const int32_t *pos = gb ? nullptr : I.pos + (size_t)tour * (size_t)n;
+  const int32_t *r = gb ? I.gb_route : ant_route(I, tour);
+  const int32_t *pos = gb ? nullptr : ant_pos(I, tour);
   int64_t s = 0;
   bool bad = false;
   for (int i = chunk * kVerifyBlock + (int)threadIdx.x; i < n; i += nchunks * kVerifyBlock) {

@@ -84,7 +84,20 @@ struct Inst {
   int32_t *routes, *pos, *ring;
   int2 *rxy;          // [A][n] coordinates of routes[a][p] (tour order)
   int64_t *lens, *cnt, *cnt_acc;
-  int64_t *ticks;     // [A][16] wall-clock ticks and call counts per phase, summed
+  int64_t *ticks;     // [A][kTicks] wall-clock ticks and call counts per phase, summed
+  // Segment-list ant tours (the local search of the single-instance kernel
+  // with seg_on): between materialisations the ant's tour is the storage
+  // arrays (route, pos, rxy of buffer `live`) read through segment records,
+  // each a storage range, its orientation and the array position of its
+  // first element, so a move rewrites records instead of elements.
+  int32_t seg_on;     // 1: the local search runs on segment lists
+  int32_t seg_shift;  // log2 of the segment length after a materialisation
+  int32_t seg_max;    // records in use that trigger a materialisation
+  int32_t *r2, *p2;   // [A][n] second storage buffer: route, pos
+  int2 *x2;           // [A][n] second storage buffer: coordinates
+  int2 *sgid;         // [A][n] (epoch, segment) of a city whose segment was split off
+  int32_t *sepoch;    // [A] last epoch of each ant
+  int32_t *rsel;      // [A] buffer holding each ant's final tour (0: routes, 1: r2)
   // tour-length verification: partial sums and route faults of the tours
   // being checked (ants 0..A-1, then the global best), the last results
   int64_t *vsum;      // [A + 1], zero between verifications
@@ -114,6 +127,19 @@ constexpr uint32_t LS_2OPT = 1u, LS_OROPT = 2u, LS_SWEEP = 4u, LS_INIT_3OPT = 8u
 constexpr int kMaxCl = 32;
 constexpr int kMaxBl = 64;
 constexpr int kMaxOrSeg = 3;
+// tick and count slots per ant (FACO_DBG_PHASE_TICKS)
+constexpr int kTicks = 24;
+// capacity of the segment record table of a segment-list tour
+constexpr int kSegCap = 2048;
+
+// Final tour of ant a (its route and positions), wherever its local search
+// left it.
+__device__ __forceinline__ const int32_t *ant_route(const Inst &I, int a) {
+  return (I.rsel[a] ? I.r2 : I.routes) + (size_t)a * (size_t)I.n;
+}
+__device__ __forceinline__ const int32_t *ant_pos(const Inst &I, int a) {
+  return (I.rsel[a] ? I.p2 : I.pos) + (size_t)a * (size_t)I.n;
+}
 
 // Element (position p, slot s) of a source-ordered table with k slots: 64
 // consecutive positions form a block, slot-major inside it, so the lanes of

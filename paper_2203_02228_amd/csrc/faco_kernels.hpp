@@ -85,7 +85,7 @@ FACO_DEV int wrap_off(int q, int off, int n) {
 constexpr int kMaxTeam = 8;
 enum TeamOp {
   OP_EXIT = 0, OP_REVERSE = 1, OP_SHIFT = 2, OP_WINDOW = 3, OP_SWEEP = 4, OP_COPY = 5,
-  OP_NEAREST = 6, OP_OROPT = 7
+  OP_NEAREST = 6, OP_OROPT = 7, OP_SEGPERM = 8, OP_SEGMAT = 9
 };
 struct TeamLds {
   int op;
@@ -99,6 +99,8 @@ struct TeamLds {
   int disp[4];                   // persistent batches: the next task
   int64_t okey[kMaxTeam][4];     // Or-opt: per-wave maxima of each listed city
   int orx[14][kWave];            // Or-opt: the leader's loaded neighbourhoods
+  int sgs[4];                    // segment-list tour: live buffer, epoch, last move's records
+  int sov[9];                    // segment-list move: link overrides
 };
 template <int TW>
 constexpr int team_words() {
@@ -857,6 +859,9 @@ FACO_DEV int64_t construct(const Inst &I, uint64_t t, int ant, bool greedy,
 // ===================================================================== //
 // Local search (Alg. 3 + Or-opt + sweep)
 // ===================================================================== //
+// Loads of a segment-list evaluation a split city may come from: the city a
+// itself, a neighbour of it, a candidate b, b's successor.
+enum { SL_A = 0, SL_NB = 1, SL_B = 2, SL_BS = 3 };
 struct Move {
   int kind;  // 0 none, 1 2-opt, 2 Or-opt
   int gain;
@@ -866,6 +871,10 @@ struct Move {
   int fpos, pq, pp, pb, side;     // positions of f, q, p, b; e = succ(b) if side 0
   int s0, s1, s2;     // segment in array order
   int2 xs0, xs1, xs2; // and its coordinates
+  // where a segment-list tour finds the cities a move splits at (2-opt: x, z;
+  // Or-opt: the segment's first city, q, the insertion edge's second city):
+  // the lane holding it and which of its loads (SegEval)
+  int ln[3], lk[3];
 };
 
 // Or-opt variants in evaluation order, one fixed slot each:
@@ -919,6 +928,9 @@ struct GroupEval {
   int64_t key2, keyo;  // group maxima: 2-opt, Or-opt (0 = none)
 };
 
+template <int GS>
+FACO_DEV void group_keys(uint32_t flags, bool act, GroupEval &R);
+
 // All loads for both move kinds of every city of the wave are issued
 // together (4 dependent levels).  Keys order candidates as the sequential
 // evaluation does: 2-opt loop 1 over the list, loop 2 over the list; Or-opt
@@ -927,7 +939,6 @@ template <int GS>
 FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
                               const int32_t *route, const int32_t *pos, const int2 *rxy) {
   const int n = I.n, K = I.k, lane = lane_id();
-  const int gb = lane & ~(GS - 1);
   const int s = lane & (GS - 1);
   const bool act = gvalid && s < K;
   const size_t row = (size_t)a * (size_t)K;
@@ -950,6 +961,19 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
   const int2 xbs = rxy[pbs], xbp = rxy[pbp];
   R.pa = pa; R.b = b; R.pb = pb; R.pbs = pbs; R.pbp = pbp; R.bs = bs; R.bp = bp;
   R.nb = nb; R.xa = xa; R.xnb = xnb; R.xb = xb; R.xbs = xbs; R.xbp = xbp; R.d_ab = d_ab;
+  group_keys<GS>(flags, act, R);
+  return R;
+}
+
+// The part of a group evaluation after the loads: neighbourhood costs and
+// the 2-opt keys.
+template <int GS>
+FACO_DEV void group_keys(uint32_t flags, bool act, GroupEval &R) {
+  const int lane = lane_id();
+  const int gb = lane & ~(GS - 1);
+  const int s = lane & (GS - 1);
+  const int2 xnb = R.xnb, xb = R.xb, xbs = R.xbs, xbp = R.xbp;
+  const int d_ab = R.d_ab;
   const int2 xas = grp_lane2<GS>(xnb, 4), xap = grp_lane2<GS>(xnb, 2);
   // Costs that depend only on the city's neighbourhood nb_0..nb_6 (tour
   // positions pa-3..pa+3), one per lane of the group: the tour edges
@@ -974,7 +998,6 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
     R.key2 = group_max<GS>(k1 > k2 ? k1 : k2);
   }
   R.keyo = 0;
-  return R;
 }
 
 // Or-opt keys for the cities of the groups with `want` set (the others get 0).
@@ -1048,6 +1071,8 @@ FACO_DEV Move extract_move(const Inst &I, const GroupEval &R, int j) {
       mv.px = pa + 1 == n ? 0 : pa + 1;
       mv.py = readlane_i(R.pb, l);
       mv.pz = readlane_i(R.pbs, l);
+      mv.ln[0] = base + 4; mv.lk[0] = SL_NB;
+      mv.ln[1] = l; mv.lk[1] = SL_BS;
     } else {         // loop 2: (pred a, a, pred b, b), flip a .. pred b
       const int l = base + idx - 32;
       mv.w = readlane_i(R.nb, base + 2); mv.x = a;
@@ -1055,6 +1080,8 @@ FACO_DEV Move extract_move(const Inst &I, const GroupEval &R, int j) {
       mv.px = pa;
       mv.py = readlane_i(R.pbp, l);
       mv.pz = readlane_i(R.pb, l);
+      mv.ln[0] = base; mv.lk[0] = SL_A;
+      mv.ln[1] = l; mv.lk[1] = SL_B;
     }
     return mv;
   }
@@ -1089,6 +1116,9 @@ FACO_DEV Move extract_move(const Inst &I, const GroupEval &R, int j) {
   mv.xs0 = readlane_i2(R.xnb, base + lf);
   mv.xs1 = readlane_i2(R.xnb, base + lf + (L > 1 ? 1 : 0));
   mv.xs2 = readlane_i2(R.xnb, base + lf + (L > 2 ? 2 : 0));
+  mv.ln[0] = base + lf; mv.lk[0] = SL_NB;
+  mv.ln[1] = base + lq; mv.lk[1] = SL_NB;
+  mv.ln[2] = l; mv.lk[2] = side ? SL_B : SL_BS;
   return mv;
 }
 
@@ -1204,6 +1234,18 @@ FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
 #undef XN
   return found;
 }
+
+// The flat tour (arrays in array order) as the sweep's test reads it.
+struct FlatT {
+  const int32_t *route, *pos;
+  const int2 *rxy;
+};
+template <int KT>
+FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x, const FlatT &T) {
+  return has_improving<KT>(I, flags, x, T.route, T.pos, T.rxy);
+}
+
+#include "faco_seg.hpp"
 
 constexpr int kChunks = 16;  // 64-element chunks in flight per wave and round
 // Rewrites of more pairs than this (elements, for block moves: twice this)
@@ -1482,21 +1524,19 @@ FACO_DEV void push_all(int n, const int *c, Queue &Q, uint32_t *inq, uint32_t *t
 // then read in ascending order and the marked cities are listed in that
 // order (and `ord` is left clear).  The tour does not change during a sweep,
 // so the order of the tests does not matter.
-template <int KT, int TW>
+template <int KT, int TW, class TT>
 FACO_DEV void sweep_part(const Inst &I, uint32_t flags, int count, int w, TeamLds *tl,
-                         uint32_t *ord, const int32_t *route, const int32_t *pos,
-                         const int2 *rxy) {
+                         uint32_t *ord, const TT &T) {
   const int i = w * kWave + lane_id();
   if (i < count) {
     const int x = tl->cities[i];
     const int ox = I.orig_of[x];
-    if (has_improving<KT>(I, flags, x, route, pos, rxy)) bit_set(ord, ox);
+    if (has_improving<KT>(I, flags, x, T)) bit_set(ord, ox);
   }
 }
 
-template <int KT, int TW>
-FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
-                   const int32_t *route, const int32_t *pos, const int2 *rxy,
+template <int KT, int TW, class TT>
+FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q, const TT &T,
                    uint32_t *inq, uint32_t *touched, uint32_t *ord, TeamLds *tl) {
   const int lane = lane_id();
   int bx = -1, bcount = 0;
@@ -1504,13 +1544,13 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q,
     if (TW == 1) {
       if (lane < cnt) {
         const int ox = I.orig_of[bx];
-        if (has_improving<KT>(I, flags, bx, route, pos, rxy)) bit_set(ord, ox);
+        if (has_improving<KT>(I, flags, bx, T)) bit_set(ord, ox);
       }
       return;
     }
     // cnt cities sit in tl->cities[0..cnt)
     team_post(tl, OP_SWEEP, cnt, (int)flags);
-    sweep_part<KT, TW>(I, flags, cnt, 0, tl, ord, route, pos, rxy);
+    sweep_part<KT, TW>(I, flags, cnt, 0, tl, ord, T);
     team_sync();
   };
   if (TW == 1) {
@@ -1659,11 +1699,12 @@ FACO_DEV void record_fault(const Inst &I, int32_t bit, int ant) {
   }
 }
 
-template <int KT, int TW>
+// SEG: the tour is a segment list (SQ); else the flat arrays route, pos, rxy.
+template <int KT, int TW, bool SEG>
 FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
                               int32_t *pos, int2 *rxy, uint32_t *inq, uint32_t *touched,
                               uint32_t *ord, TeamLds *tl, int W, Queue Q, LaneCounters &cnt,
-                              LaneCounters &tk, int ant) {
+                              LaneCounters &tk, int ant, SegState &SQ) {
   constexpr int GS = KT <= 16 ? 16 : 32;  // lanes per evaluated city
   constexpr int G = kWave / GS;           // cities evaluated together
   const int n = I.n, lane = lane_id();
@@ -1703,7 +1744,12 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
 #pragma unroll
       for (int g = 1; g < G; ++g) a = grp == g ? e[g] : a;
       const int64_t t0 = fine_ticks();
-      GroupEval R = eval_group<GS>(I, flags, a, grp < gcount, route, pos, rxy);
+      SegEval Z;
+      GroupEval R;
+      if constexpr (SEG)
+        R = eval_group_seg<GS>(I, flags, a, grp < gcount, SQ.T, Z);
+      else
+        R = eval_group<GS>(I, flags, a, grp < gcount, route, pos, rxy);
       // Or-opt is only tried where no 2-opt move exists, and only cities
       // before the first one with a 2-opt move can be the chosen one
       const uint64_t h2 = ballot((lane & (GS - 1)) == 0 && grp < gcount && R.key2 > 0);
@@ -1750,22 +1796,32 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       const Move mv = extract_move<GS>(I, R, j);
       const int64_t ta = fine_ticks();
       if (uniform_i(mv.kind) == 1) {
-        cnt[CNT_MOVED_ELEMS] += apply_2opt<TW>(n, uniform_i(mv.px), uniform_i(mv.py),
-                                               uniform_i(mv.pz), tl, route, pos, rxy);
+        if constexpr (SEG)
+          cnt[CNT_MOVED_ELEMS] += seg_apply_2opt<TW>(I, SQ, tl, mv, Z, tk);
+        else
+          cnt[CNT_MOVED_ELEMS] += apply_2opt<TW>(n, uniform_i(mv.px), uniform_i(mv.py),
+                                                 uniform_i(mv.pz), tl, route, pos, rxy);
         tk[15] += fine_ticks() - ta;
         const int pc[4] = {mv.w, mv.x, mv.y, mv.z};
         push_all<4>(n, pc, Q, inq, touched);
         cnt[CNT_MOVES_2OPT]++;
       } else {
-        cnt[CNT_MOVED_ELEMS] +=
-            apply_oropt<TW>(n, uniform_i(mv.L), mv.a, mv.f, mv.b, mv.e, uniform_i(mv.side),
-                            uniform_i(mv.pb), uniform_i(mv.fpos), uniform_i(mv.pq),
-                            uniform_i(mv.pp), mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2, tl,
-                            route, pos, rxy);
+        if constexpr (SEG)
+          cnt[CNT_MOVED_ELEMS] += seg_apply_oropt<TW>(I, SQ, tl, mv, Z, tk);
+        else
+          cnt[CNT_MOVED_ELEMS] +=
+              apply_oropt<TW>(n, uniform_i(mv.L), mv.a, mv.f, mv.b, mv.e, uniform_i(mv.side),
+                              uniform_i(mv.pb), uniform_i(mv.fpos), uniform_i(mv.pq),
+                              uniform_i(mv.pp), mv.s0, mv.s1, mv.s2, mv.xs0, mv.xs1, mv.xs2,
+                              tl, route, pos, rxy);
         tk[15] += fine_ticks() - ta;
         const int pc[6] = {mv.p, mv.q, mv.b, mv.e, mv.f, mv.l};
         push_all<6>(n, pc, Q, inq, touched);
         cnt[CNT_MOVES_OROPT]++;
+      }
+      if constexpr (SEG) {
+        // room for the next move's splits
+        if (uniform_i(SQ.S) + 3 > I.seg_max) seg_materialize<TW>(I, ant < 0 ? 0 : ant, SQ, tl, tk);
       }
       tk[2] += fine_ticks() - t1;
       ++changes;
@@ -1783,8 +1839,12 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     changes_at_sweep = changes;
     cnt[CNT_SWEEPS]++;
     const int64_t t2 = ticks();
-    const int pushed =
-        uniform_i(sweep<KT, TW>(I, flags, W, Q, route, pos, rxy, inq, touched, ord, tl));
+    int pushed;
+    if constexpr (SEG)
+      pushed = uniform_i(sweep<KT, TW>(I, flags, W, Q, SQ.T, inq, touched, ord, tl));
+    else
+      pushed = uniform_i(sweep<KT, TW>(I, flags, W, Q, FlatT{route, pos, rxy}, inq, touched,
+                                       ord, tl));
     tk[3] += ticks() - t2;
     if (pushed == 0) break;
   }
@@ -1796,11 +1856,18 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
 // Helper waves of a team: wait for a command, take this wave's share, repeat
 // until the leader posts OP_EXIT.
 // ===================================================================== //
-template <int KT, int TW>
+template <int KT, int TW, bool SEG>
 FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *vis,
-                          uint32_t *ord, int32_t *route, int32_t *pos, int2 *rxy) {
+                          uint32_t *ord, int32_t *route, int32_t *pos, int2 *rxy, int4 *rec) {
   Draws D;
+  // a segment-list move's record whose cities this wave labels after the move
+  int rl_h = -1, rl_lo = 0, rl_hi = -1;
+  SegT rl_T;
   for (;;) {
+    if (SEG && rl_h >= 0) {
+      seg_relabel(rl_T, rl_lo, rl_hi, rl_h);
+      rl_h = -1;
+    }
     team_sync();
     const int op = uniform_i(tl->op);
     if (op == OP_EXIT) break;
@@ -1824,8 +1891,47 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
       int mj;
       nearest_part<TW>(I, team_arg(tl, 0), w, vis, tl, md, mj);
     } else if (op == OP_SWEEP) {
-      sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, ord, route,
-                         pos, rxy);
+      if constexpr (SEG)
+        sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, ord,
+                           seg_view(I, ant, rec, uniform_i(tl->sgs[0]), uniform_i(tl->sgs[1]),
+                                    uniform_i(tl->sgs[2]), uniform_i(tl->sgs[3])));
+      else
+        sweep_part<KT, TW>(I, (uint32_t)team_arg(tl, 1), team_arg(tl, 0), w, tl, ord,
+                           FlatT{route, pos, rxy});
+    } else if (SEG && op == OP_SEGPERM) {
+      const SegT T = seg_view(I, ant, rec, uniform_i(tl->sgs[0]), uniform_i(tl->sgs[1]));
+      const int rv = team_arg(tl, 5);
+      const int S0 = team_arg(tl, 0), S = team_arg(tl, 1);
+      // the new record this wave labels: read before the pass's barrier (the
+      // leader may change records again once the move is over)
+      if (S0 + w - 1 < S) {
+        const int4 r = rec[S0 + w - 1];
+        rl_h = S0 + w - 1;
+        rl_lo = uniform_i(r.x);
+        rl_hi = uniform_i(r.y);
+        rl_T = T;
+      }
+      SegOv O;
+#pragma unroll
+      for (int j = 0; j < kSovPre + kSovPost; ++j) O.v[j] = uniform_i(tl->sov[j]);
+      seg_perm_part(T, w * kWave + lane_id(), kWave * TW, S, team_arg(tl, 2), team_arg(tl, 3),
+                    team_arg(tl, 4), rv & 1, (rv >> 1) & 1, O, team_arg(tl, 6),
+                    team_arg(tl, 7));
+      if (!FACO_SEG_DEFER && rl_h >= 0) {
+        seg_relabel(rl_T, rl_lo, rl_hi, rl_h);
+        rl_h = -1;
+      }
+    } else if (SEG && op == OP_SEGMAT) {
+      const int live = uniform_i(tl->sgs[0]);
+      const SegT T = seg_view(I, ant, rec, live, uniform_i(tl->sgs[1]), uniform_i(tl->sgs[2]),
+                              uniform_i(tl->sgs[3]));
+      const size_t o = (size_t)ant * (size_t)I.n;
+      const int tid = w * kWave + lane_id();
+      seg_mat_part(T, tid, kWave * TW, (live ? I.routes : I.r2) + o, (live ? I.rxy : I.x2) + o,
+                   (live ? I.pos : I.p2) + o);
+      team_sync();
+      seg_reset_part(rec, tid, kWave * TW, (I.n + (1 << I.seg_shift) - 1) >> I.seg_shift, I.n,
+                     I.seg_shift);
     } else if (op == OP_OROPT) {
       oropt_part<KT, TW>(I, w, tl);
     }
@@ -1837,9 +1943,13 @@ FACO_DEV void team_helper(const Inst &I, int ant, int w, TeamLds *tl, uint32_t *
 // One ant: construction + local search.  mode 0: ant `ant` of iteration
 // st->iter + 1.  mode 1: initial solution (nearest neighbour + LS over all
 // cities) written to the global best.
-//   lds: [team area][visited W][listed W][sweep order W][queue ring I.lcap].
+//   lds: [team area][visited W][listed W][sweep order W]
+//        [SEG: segment records, I.seg_max int4 at a 16-byte boundary]
+//        [queue ring I.lcap].
 // ===================================================================== //
-template <int KT, int TW>
+__host__ __device__ inline int seg_lds_words(int tw_words, int W) { return (tw_words + 3 * W + 3) & ~3; }
+
+template <int KT, int TW, bool SEG = false>
 FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   const int n = I.n, lane = lane_id();
   const int W = (n + 31) >> 5;
@@ -1847,6 +1957,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   uint32_t *vis = lds + team_words<TW>();
   uint32_t *inq = vis + W;
   uint32_t *ord = inq + W;
+  int4 *rec = (int4 *)(lds + seg_lds_words(team_words<TW>(), W));
   int32_t *route = I.routes + (size_t)ant * (size_t)n;
   int32_t *pos = I.pos + (size_t)ant * (size_t)n;
   int32_t *ring = I.ring + (size_t)ant * (size_t)n;
@@ -1854,7 +1965,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   if (TW > 1) {
     const int w = uniform_i((int)(threadIdx.x >> 6));
     if (w > 0) {
-      team_helper<KT, TW>(I, ant, w, tl, vis, ord, route, pos, rxy);
+      team_helper<KT, TW, SEG>(I, ant, w, tl, vis, ord, route, pos, rxy, rec);
       return;
     }
   }
@@ -1869,7 +1980,7 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   uint32_t flags = I.ls_flags;
   const int lcap = I.lcap;
   Queue Q;
-  Q.lr = (int32_t *)(ord + W);
+  Q.lr = SEG ? (int32_t *)(rec + I.seg_max) : (int32_t *)(ord + W);
   Q.gr = ring;
   if (init) {
     // the initial solution reports only its local-search counters
@@ -1912,36 +2023,48 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
   Q.count = uniform_i(Q.count);
   Q.cap = uniform_i(Q.cap);
   Q.in_lds = uniform_i(Q.in_lds);
+  SegState SQ;
+  if constexpr (SEG) seg_begin(I, ant, rec, tl, TW > 1, SQ);
   if (flags & (LS_2OPT | LS_OROPT))
-    len -= local_search<KT, TW>(I, flags, route, pos, rxy, inq, vis, ord, tl, W, Q, cnt, tk,
-                                init ? -1 : ant);
+    len -= local_search<KT, TW, SEG>(I, flags, route, pos, rxy, inq, vis, ord, tl, W, Q, cnt,
+                                     tk, init ? -1 : ant, SQ);
+  int live = 0;
+  if constexpr (SEG) {
+    if (uniform_i(SQ.dirty)) seg_materialize<TW>(I, ant, SQ, tl, tk);
+    live = uniform_i(SQ.live);
+    if (lane == 0) I.sepoch[ant] = SQ.T.epoch;
+  }
   if (TW > 1) {
     if (lane == 0) tl->op = OP_EXIT;
     team_sync();
   }
   if (init) {
-    for (int i = lane; i < n; i += kWave) I.gb_route[i] = route[i];
+    const int32_t *fr = (live ? I.r2 : I.routes) + (size_t)ant * (size_t)n;
+    for (int i = lane; i < n; i += kWave) I.gb_route[i] = fr[i];
     if (lane == 0) {
       I.st->gb_len = len;
       I.st->init_len = len;
     }
     if (lane < NCNT) I.st->init_cnt[lane] = cnt.v;
   } else {
-    if (lane == 0) I.lens[ant] = len;
+    if (lane == 0) {
+      I.lens[ant] = len;
+      I.rsel[ant] = live;
+    }
     if (lane < NCNT) {
       I.cnt[(size_t)ant * NCNT + lane] = cnt.v;
       I.cnt_acc[(size_t)ant * NCNT + lane] += cnt.v;
     }
     tk[4] = ticks() - t0;
-    if (lane < 16) I.ticks[(size_t)ant * 16 + lane] += tk.v;
+    if (lane < kTicks) I.ticks[(size_t)ant * kTicks + lane] += tk.v;
   }
 }
 
 // One workgroup of TW waves per ant.
-template <int KT, int TW>
+template <int KT, int TW, bool SEG = false>
 __global__ void __launch_bounds__(64 * TW) ant_kernel(Inst I, int mode) {
   extern __shared__ uint32_t lds[];
-  run_ant<KT, TW>(I, (int)blockIdx.x, mode, lds);
+  run_ant<KT, TW, SEG>(I, (int)blockIdx.x, mode, lds);
 }
 
 // ===================================================================== //

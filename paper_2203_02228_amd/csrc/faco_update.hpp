@@ -73,7 +73,7 @@ FACO_DEV void run_source(const Inst &I, int i, int init) {
   if (init) {
     from = I.gb_route;
   } else {
-    const int32_t *ibr = I.routes + (size_t)st->ib * (size_t)n;
+    const int32_t *ibr = ant_route(I, st->ib);
     from = (st->src_gb && !st->improved) ? I.gb_route : ibr;
   }
   const int node = from[i], next = from[i1], prev = from[i0];

@@ -19,7 +19,8 @@ FACO_LS_2OPT, FACO_LS_OROPT, FACO_LS_SWEEP, FACO_LS_INIT_3OPT = 1, 2, 4, 8
  FACO_DBG_LIMITS, FACO_DBG_COUNTERS, FACO_DBG_CAND_LISTS, FACO_DBG_BACKUP_LISTS,
  FACO_DBG_HEURISTIC, FACO_DBG_INFO, FACO_DBG_INIT_COUNTERS,
  FACO_DBG_COUNTER_TOTALS, FACO_DBG_PHASE_TICKS, FACO_DBG_TEAM_WAVES, FACO_DBG_FAULT,
- FACO_DBG_RECOMPUTED_LENGTHS) = range(16)
+ FACO_DBG_RECOMPUTED_LENGTHS, FACO_DBG_TOUR) = range(17)
+FACO_NTICKS = 24  # tick and count slots per ant (FACO_DBG_PHASE_TICKS)
 FACO_FAULT_LS_STALL, FACO_FAULT_LENGTH, FACO_FAULT_PERMUTATION = 1, 2, 4
 CNT_NAMES = ["aco_steps", "copied", "backup", "fallback", "new_edges",
              "ls_pops", "moves_2opt", "moves_oropt", "moved_elems", "sweeps",
@@ -31,7 +32,8 @@ EXPORTED = ["faco_build_instance", "faco_run_iterations", "faco_get_best_tour",
             "faco_debug_get", "faco_footprint_bytes", "faco_set_timing",
             "faco_phase_times", "faco_set_batch_ants_per_block", "faco_set_team_waves",
             "faco_set_queue_lds_capacity", "faco_set_verify", "faco_run_batch_noalloc",
-            "faco_set_batch_config", "faco_get_batch_config", "faco_autotune_batch"]
+            "faco_set_batch_config", "faco_get_batch_config", "faco_autotune_batch",
+            "faco_set_tour_segments"]
 
 
 class faco_params(ctypes.Structure):
@@ -111,6 +113,8 @@ def lib():
         L.faco_set_team_waves.argtypes = [ctypes.c_int32]
         L.faco_set_queue_lds_capacity.restype = ctypes.c_int
         L.faco_set_queue_lds_capacity.argtypes = [ctypes.c_int32]
+        L.faco_set_tour_segments.restype = ctypes.c_int
+        L.faco_set_tour_segments.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.faco_set_verify.restype = ctypes.c_int
         L.faco_set_verify.argtypes = [vp, ctypes.c_int32]
         L.faco_phase_times.restype = ctypes.c_int
@@ -240,6 +244,13 @@ def faco_set_queue_lds_capacity(cap):
     _check(lib().faco_set_queue_lds_capacity(int(cap)))
 
 
+def faco_set_tour_segments(mode, length_log2=0, max_records=0):
+    """Tour representation of the local search for instances built afterwards:
+    mode 0 by size, 1 flat arrays, 2 segment lists; segment length
+    2**length_log2 (0: by size); record limit (0: 2048)."""
+    _check(lib().faco_set_tour_segments(int(mode), int(length_log2), int(max_records)))
+
+
 def faco_set_team_waves(tw):
     """Waves per ant for instances built afterwards (0 = by size; 1, 4, 8)."""
     _check(lib().faco_set_team_waves(int(tw)))
@@ -286,10 +297,11 @@ def faco_debug_get(inst, what):
         FACO_DBG_INFO: (np.int64, (8,)),
         FACO_DBG_INIT_COUNTERS: (np.int64, (FACO_NCNT,)),
         FACO_DBG_COUNTER_TOTALS: (np.int64, (A, FACO_NCNT)),
-        FACO_DBG_PHASE_TICKS: (np.int64, (A, 16)),
+        FACO_DBG_PHASE_TICKS: (np.int64, (A, FACO_NTICKS)),
         FACO_DBG_TEAM_WAVES: (np.int32, (1,)),
         FACO_DBG_FAULT: (np.int64, (4,)),
         FACO_DBG_RECOMPUTED_LENGTHS: (np.int64, (A + 1,)),
+        FACO_DBG_TOUR: (np.int64, (3,)),
     }
     dt, shape = shapes[what]
     out = np.zeros(shape, dtype=dt)

@@ -58,6 +58,8 @@ def test_checker_accepts_uniform_barrier(tmp_path):
 
 @pytest.mark.parametrize("inst", [
     "template __global__ void faco::ant_kernel<16, 8>(faco::Inst, int);",
+    # the same kernel on segment-list tours (team moves and materialisations)
+    "template __global__ void faco::ant_kernel<16, 8, true>(faco::Inst, int);",
     # the persistent batched kernel: dispatch loop, ant, update, all on barriers
     "template __global__ void faco::ant_persist_kernel<16, 8>(const faco::Inst *, "
     "faco::BatchCtl *, faco::BatchRun *, int);",
