@@ -180,15 +180,24 @@ def run_batch_mode(args):
     iters = args.batch_iterations or ws[0].iterations
     pts = gen_points_parallel([(w.kind, w.n, w.instance_seed) for w in ws])
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+    # a stream of its own (not the legacy default stream, which orders itself
+    # against the library's streams)
+    stream = torch.cuda.Stream()
     hs = [F.faco_build_instance(p, stream=stream, **w.params()) for p, w in zip(pts, ws)]
     torch.cuda.synchronize()
     # the library's autotuner times every configuration on twins of the batch
     # and stores the fastest for this size class
     t0 = time.perf_counter()
-    tuned = F.faco_autotune_batch(hs, trial_iterations=args.tune_iterations, stream=stream)
+    if args.batch_config:
+        # a given configuration instead of the autotuner's
+        keys = ["persistent", "team_waves", "ants_per_block", "queue_lds_capacity",
+                "big_percent", "big_team_waves"]
+        tuned = dict(zip(keys, [int(x) for x in args.batch_config.split(",")]))
+        F.faco_set_batch_config(**tuned)
+    else:
+        tuned = F.faco_autotune_batch(hs, trial_iterations=args.tune_iterations, stream=stream)
     tune_s = time.perf_counter() - t0
-    log(f"batch autotune ({tune_s:.1f} s) -> {tuned}")
+    log(f"batch configuration ({tune_s:.1f} s) -> {tuned}")
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -380,6 +389,9 @@ def main():
     ap.add_argument("--batch-iterations", type=int, default=0)
     ap.add_argument("--batch-seq-count", type=int, default=32)
     ap.add_argument("--tune-iterations", type=int, default=30)
+    ap.add_argument("--batch-config", default="",
+                    help="persistent,team_waves,ants_per_block,queue_lds_capacity,big_percent,"
+                         "big_team_waves: run the batch with this configuration, untuned")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--chunk", type=int, default=10)
@@ -389,6 +401,8 @@ def main():
     ap.add_argument("--result-timeout", type=float, default=900.0)
     ap.add_argument("--team-waves", type=int, default=0,
                     help="waves per ant (0 = the library's choice by size; 1, 4, 8)")
+    ap.add_argument("--tour-segments", type=int, default=0,
+                    help="local-search tour: 0 or 1 flat arrays, 2 segment lists")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied once by a plain device-to-device copy kernel before "
                          "the workload (scales hardware byte counters)")
@@ -428,6 +442,7 @@ def main():
         del src, dst
     stream = torch.cuda.current_stream()
     F.faco_set_team_waves(args.team_waves)
+    F.faco_set_tour_segments(args.tour_segments)
     t0 = time.time()
     g = F.faco_build_instance(xy, stream=stream, **params)
     build_s = time.time() - t0
@@ -467,7 +482,20 @@ def main():
     best_tour, best_len = F.faco_get_best_tour(g)
     lengths_ok = bool(np.array_equal(rec[:-1], lens) and rec[-1] == best_len and fault[0] == 0)
     info = F.faco_debug_get(g, F.FACO_DBG_INFO)
+    tour = F.faco_debug_get(g, F.FACO_DBG_TOUR)
     g.close()
+    tour_cfg = ("flat arrays" if not tour[0] else
+                f"segment lists (length {int(tour[1])}, {int(tour[2])} records)")
+    seg_stats = None
+    if tour[0]:
+        # per ant and iteration: materialisations, their time, splits,
+        # relabelled cities, leader / team time of moves
+        seg_stats = {"materialisations": round(float(per[16]), 2),
+                     "materialise_us": round(float(per[17]) / 100.0, 1),
+                     "splits": round(float(per[19]), 1),
+                     "relabelled": round(float(per[18]), 1),
+                     "move_leader_us": round(float(per[21]) / 100.0, 1),
+                     "move_team_us": round(float(per[22]) / 100.0, 1)}
 
     ms_per_step = total_ms / args.steps
     ant_ms = phase_ms[0] / max(1, launches[0])
@@ -475,6 +503,9 @@ def main():
     achieved = (bytes_survey / launches_ant) / (ant_ms * 1e-3) / 1e9
     achieved_lb = (bytes_lb / launches_ant) / (ant_ms * 1e-3) / 1e9
     traffic, traffic_src = profiled_traffic(w.name, args.warmup, args.steps)
+    if tour[0]:
+        traffic, traffic_src = None, "counter profile taken with flat-array tours"
+
     value = A * args.steps / (total_ms * 1e-3)
     out = {
         "metric": "ant-tours/s (construct+2-opt/Or-opt) at 100k cities",
@@ -494,12 +525,14 @@ def main():
                    "local_search": "2-opt+Or-opt+sweep", "iterations_timed":
                    f"{args.warmup + 1}..{args.warmup + args.steps}",
                    "best_length": int(best_len), "iterations_done": int(info[0]),
-                   "waves_per_ant": team_waves, "build_s": round(build_s, 2)},
+                   "waves_per_ant": team_waves, "tour": tour_cfg,
+                   "build_s": round(build_s, 2)},
         "lengths_verified": lengths_ok,
         "device_faults": int(fault[0]),
         "per_ant_us": tk_us,
         "per_ant_calls": tk_calls,
         "slowest_ant_us": slowest_us,
+        "segment_lists": seg_stats,
         "per_ant_counters": {name: round(v, 1) for name, v in zip(F.CNT_NAMES, cnt_mean)},
         "phase_ms_per_iteration": {name: round(phase_ms[i] / max(1, launches[i]), 4)
                                    for i, name in enumerate(["ants", "colony", "source",

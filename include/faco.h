@@ -187,9 +187,11 @@ int faco_get_batch_config(faco_batch_config *config);
 /* Autotuner: times faco_run_batch over `trial_iterations` iterations with
  * each candidate configuration (per phase with 1/4/8 waves per ant, 1/2 ants
  * per workgroup for one-wave ants, LDS queue capacity as built or 2048;
- * persistent with 4/8-wave teams; the largest 15% or 30% of the instances
- * split off with 4-wave teams) on twins of the handles built from their own
- * inputs (the handles do not advance), keeps the fastest, and stores it
+ * persistent with 4/8-wave teams; the largest 10/15/20/30% of the instances
+ * split off with 4- or 8-wave teams) on twins of the handles built from their
+ * own inputs (the handles do not advance); the candidates take turns in three
+ * rounds, so each is timed over the same stretch of the twins' run; keeps the
+ * fastest, and stores it
  * for the batch's size class (the longest tour's power of two): later
  * faco_run_batch calls use the stored configuration of their own class,
  * else of the nearest stored one.  best_out (may be NULL) receives it.  Synchronises hip_stream.

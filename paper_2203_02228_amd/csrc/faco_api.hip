@@ -974,8 +974,11 @@ static hipError_t ws_grow(T *&ptr, size_t &cap, size_t want) {
 
 // One batch call with an explicit configuration.
 // One (sub-)batch with an explicit configuration.  Caller holds g_batch_mu.
+// handles: order the batch after the work already on the handles' own
+// streams, and their later work after the batch (a split does that once for
+// both of its parts).
 static int run_batch_one(faco_instance *const *hs, int32_t count, int32_t iterations,
-                         hipStream_t st, const faco_batch_config &cfg) {
+                         hipStream_t st, const faco_batch_config &cfg, bool handles = true) {
   BatchWs &g_ws = g_ws_map[st];
   hipError_t e;
 #define BT(expr)                                                                      \
@@ -1002,7 +1005,7 @@ static int run_batch_one(faco_instance *const *hs, int32_t count, int32_t iterat
     if (!g_ws.run) BT(hipMalloc((void **)&g_ws.run, sizeof(faco::BatchRun)));
   }
   // order after the handles' own streams
-  for (int32_t i = 0; i < count; ++i) {
+  for (int32_t i = 0; i < count && handles; ++i) {
     if (hs[i]->stream == st) continue;
     hipEvent_t ev;
     BT(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1074,7 +1077,7 @@ static int run_batch_one(faco_instance *const *hs, int32_t count, int32_t iterat
   }
   // later calls on each handle's stream, and the next batch, come after this one
   BT(hipEventRecord(g_ws.last_done, st));
-  for (int32_t i = 0; i < count; ++i)
+  for (int32_t i = 0; i < count && handles; ++i)
     if (hs[i]->stream != st) BT(hipStreamWaitEvent(hs[i]->stream, g_ws.last_done, 0));
 #undef BT
   return FACO_OK;
@@ -1082,15 +1085,16 @@ static int run_batch_one(faco_instance *const *hs, int32_t count, int32_t iterat
 
 // A second stream per batch stream, for the large instances of a split batch.
 struct SplitStream {
-  hipStream_t s = nullptr;
-  hipEvent_t start = nullptr, done = nullptr;
+  hipStream_t s = nullptr, s2 = nullptr;  // the big and the small part
+  hipEvent_t start = nullptr, done = nullptr, done2 = nullptr;
 };
 static std::map<hipStream_t, SplitStream> g_split_map;
 
 // One batch call with an explicit configuration: the whole batch at once, or
 // (big_percent > 0) the largest instances as a sub-batch of their own (waves
-// per ant big_team_waves) on a second stream beside the rest, the call still
-// ordered on st.
+// per ant big_team_waves) beside the rest, each part on a non-blocking stream
+// of the library (the caller's stream may be the legacy default stream, which
+// would serialise with the other part), the call still ordered on st.
 static int run_batch_cfg(faco_instance *const *hs, int32_t count, int32_t iterations,
                          hipStream_t st, const faco_batch_config &cfg) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
@@ -1106,27 +1110,49 @@ static int run_batch_cfg(faco_instance *const *hs, int32_t count, int32_t iterat
   SplitStream &sp = g_split_map[st];
   if (!sp.s) {
     BT(hipStreamCreateWithFlags(&sp.s, hipStreamNonBlocking));
+    BT(hipStreamCreateWithFlags(&sp.s2, hipStreamNonBlocking));
     BT(hipEventCreateWithFlags(&sp.start, hipEventDisableTiming));
     BT(hipEventCreateWithFlags(&sp.done, hipEventDisableTiming));
+    BT(hipEventCreateWithFlags(&sp.done2, hipEventDisableTiming));
   }
-  // the second stream starts after the work already on st and ends before
-  // anything enqueued on st later
+  // both streams start after the work already on st and on the handles' own
+  // streams, and end before anything enqueued on them later (once for both
+  // parts: a part that waited for the handles' streams after the other part
+  // had been ordered before them would wait for that whole part)
+  std::vector<hipStream_t> hstreams;
+  for (int32_t i = 0; i < count; ++i)
+    if (hs[i]->stream != st &&
+        std::find(hstreams.begin(), hstreams.end(), hs[i]->stream) == hstreams.end())
+      hstreams.push_back(hs[i]->stream);
   BT(hipEventRecord(sp.start, st));
   BT(hipStreamWaitEvent(sp.s, sp.start, 0));
+  BT(hipStreamWaitEvent(sp.s2, sp.start, 0));
+  for (hipStream_t hx : hstreams) {
+    hipEvent_t ev;
+    BT(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    BT(hipEventRecord(ev, hx));
+    BT(hipStreamWaitEvent(sp.s, ev, 0));
+    BT(hipStreamWaitEvent(sp.s2, ev, 0));
+    BT(hipEventDestroy(ev));
+  }
   faco_batch_config big = cfg;
   big.persistent = 0;
   big.team_waves = cfg.big_team_waves;
   big.big_percent = 0;
   faco_batch_config small = cfg;
   small.big_percent = 0;
-  int rc = run_batch_one(order.data(), nbig, iterations, sp.s, big);
+  int rc = run_batch_one(order.data(), nbig, iterations, sp.s, big, false);
   if (rc) return rc;
-  rc = run_batch_one(order.data() + nbig, count - nbig, iterations, st, small);
+  rc = run_batch_one(order.data() + nbig, count - nbig, iterations, sp.s2, small, false);
   if (rc) return rc;
   BT(hipEventRecord(sp.done, sp.s));
+  BT(hipEventRecord(sp.done2, sp.s2));
   BT(hipStreamWaitEvent(st, sp.done, 0));
-  for (int32_t i = 0; i < nbig; ++i)
-    if (order[(size_t)i]->stream != st) BT(hipStreamWaitEvent(order[(size_t)i]->stream, sp.done, 0));
+  BT(hipStreamWaitEvent(st, sp.done2, 0));
+  for (hipStream_t hx : hstreams) {
+    BT(hipStreamWaitEvent(hx, sp.done, 0));
+    BT(hipStreamWaitEvent(hx, sp.done2, 0));
+  }
 #undef BT
   return FACO_OK;
 }
@@ -1175,7 +1201,7 @@ extern "C" int faco_autotune_batch(faco_instance *const *hs, int32_t count,
     twins.push_back(t);
   }
   // per phase: waves per ant, ants per workgroup, queue capacity; persistent
-  // teams; the largest 15% or 30% split off with 4-wave teams
+  // teams; the largest 10% .. 30% split off with 4- or 8-wave teams
   std::vector<faco_batch_config> cand;
   for (int tw : {1, 4, 8})
     for (int apb : {1, 2})
@@ -1185,32 +1211,40 @@ extern "C" int faco_autotune_batch(faco_instance *const *hs, int32_t count,
       }
   for (int tw : {4, 8}) cand.push_back({1, tw, 1, 2048, 0, 0});
   if (count >= 4)
-    for (int pct : {15, 30}) cand.push_back({0, 1, 1, 2048, pct, 4});
+    for (int pct : {10, 15, 20, 30})
+      for (int btw : {4, 8}) cand.push_back({0, 1, 1, 2048, pct, btw});
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     drop();
     return set_err(nullptr, FACO_EDEVICE, "hipEventCreate failed");
   }
-  float best_ms = 0.0f;
-  faco_batch_config best = g_batch_cfg;
-  bool have = false;
+  // The twins advance with every trial, and the work per iteration changes
+  // along a run: the candidates take turns in rounds, so that each is timed
+  // over the same stretch of iterations.
+  const int rounds = trial_iterations >= 3 ? 3 : 1;
+  std::vector<float> total(cand.size(), 0.0f);
   int rc = FACO_OK;
-  for (const faco_batch_config &c : cand) {
-    if (hipEventRecord(e0, st) != hipSuccess) { rc = FACO_EDEVICE; break; }
-    rc = run_batch_cfg(twins.data(), count, trial_iterations, st, c);
-    if (rc) break;
-    float ms = 0.0f;
-    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      rc = set_err(nullptr, FACO_EDEVICE, "timing a trial failed");
-      break;
-    }
-    if (!have || ms < best_ms) {
-      best_ms = ms;
-      best = c;
-      have = true;
+  for (int r = 0; r < rounds && rc == FACO_OK; ++r) {
+    const int its = trial_iterations / rounds + (r < trial_iterations % rounds ? 1 : 0);
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = FACO_EDEVICE; break; }
+      rc = run_batch_cfg(twins.data(), count, its, st, cand[ci]);
+      if (rc) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = set_err(nullptr, FACO_EDEVICE, "timing a trial failed");
+        break;
+      }
+      total[ci] += ms;
     }
   }
+  faco_batch_config best = g_batch_cfg;
+  for (size_t ci = 0, bi = 0; ci < cand.size() && rc == FACO_OK; ++ci)
+    if (ci == 0 || total[ci] < total[bi]) {
+      bi = ci;
+      best = cand[ci];
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   drop();
