@@ -269,9 +269,10 @@ def run_served_mode(args):
         per_class = {}
         for (_, w), p in zip(reqs, pts):
             c = srv._class_of(w.n)
-            if len(per_class.setdefault(c, [])) < 3:
+            if len(per_class.setdefault(c, [])) < args.serve_tune_samples:
                 per_class[c].append((p, w.params()))
-        tuned = srv.tune([x for v in per_class.values() for x in v])
+        tuned = srv.tune([x for v in per_class.values() for x in v],
+                         trial_iterations=args.serve_tune_iterations)
         tune_s = time.perf_counter() - t0
         log(f"served: per-class autotune ({tune_s:.1f} s) -> {tuned}")
     t0 = time.perf_counter()
@@ -403,6 +404,9 @@ def main():
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB for resident solves")
     ap.add_argument("--seq-sample", type=int, default=16)
     ap.add_argument("--serve-tune", type=int, default=1)
+    ap.add_argument("--serve-tune-samples", type=int, default=8,
+                    help="requests per size class the served autotune times")
+    ap.add_argument("--serve-tune-iterations", type=int, default=6)
     ap.add_argument("--result-timeout", type=float, default=900.0)
     ap.add_argument("--team-waves", type=int, default=0,
                     help="waves per ant (0 = the library's choice by size; 1, 4, 8)")
