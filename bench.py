@@ -355,6 +355,35 @@ def run_iterations_timed(F, g, stream, steps, torch, label):
     return ev0.elapsed_time(ev1)
 
 
+def slowest_ants(F, stream, w, warmup, steps, torch):
+    """The same window on a fresh build, one iteration at a time: the phase
+    times of each iteration's slowest ant (it sets the launch time), averaged
+    over the window, beside the median ant's.  Outside the timed region."""
+    g = F.faco_build_instance(w.points(), stream=stream, **w.params())
+    F.faco_run_iterations(g, warmup)
+    torch.cuda.synchronize()
+    names = {0: "construct", 1: "ls_eval", 2: "ls_apply", 15: "ls_rewrite", 3: "sweep",
+             4: "ant_total"}
+    prev = F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS).astype(np.int64)
+    cprev = F.faco_debug_get(g, F.FACO_DBG_COUNTER_TOTALS).astype(np.int64)
+    slow, med = [], []
+    for _ in range(steps):
+        F.faco_run_iterations(g, 1)
+        tk = F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS).astype(np.int64)
+        c = F.faco_debug_get(g, F.FACO_DBG_COUNTER_TOTALS).astype(np.int64)
+        d, dc = tk - prev, c - cprev
+        prev, cprev = tk, c
+        order = np.argsort(d[:, 4])
+        for a, out in ((order[-1], slow), (order[len(order) // 2], med)):
+            row = {v: d[a, k] / 100.0 for k, v in names.items()}
+            row["moves"] = dc[a, 6] + dc[a, 7]
+            row["moved_elems"] = dc[a, 8]
+            out.append(row)
+    g.close()
+    avg = lambda rows: {k: round(float(np.mean([r[k] for r in rows])), 1) for k in rows[0]}
+    return {"slowest": avg(slow), "median": avg(med)}
+
+
 def full_run(F, I, torch, stream, w):
     """The configured run: all of the workload's iterations from a fresh build,
     with every tour length recomputed and checked on the device in every
@@ -388,6 +417,8 @@ def main():
     ap.add_argument("--workload", default="stipple100k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-run", action="store_true")
+    ap.add_argument("--no-slowest", action="store_true",
+                    help="skip the per-iteration slowest-ant breakdown")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -562,6 +593,9 @@ def main():
         log(f"full run: {w.iterations} iterations from a fresh build, verification on ...")
         out["full_run"] = full_run(F, I, torch, stream, w)
         log(f"full run: {out['full_run']}")
+    if not args.no_slowest:
+        log("slowest ant of each iteration over the same window (fresh build) ...")
+        out["ants_by_iteration_us"] = slowest_ants(F, stream, w, args.warmup, args.steps, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xy, params, args.warmup, args.steps, args.cpu_budget)
     if not args.no_batch:
