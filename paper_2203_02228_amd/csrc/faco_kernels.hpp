@@ -965,6 +965,58 @@ FACO_DEV GroupEval eval_group(const Inst &I, uint32_t flags, int a, bool gvalid,
   return R;
 }
 
+// The loads of a group that never change along a local search: the city's
+// candidate row (candidate and cost) and its coordinates.  Loaded for the
+// next group while the current move is applied.
+struct GroupStatic {
+  int a;       // the group's city (-1: none)
+  int b, d_ab;
+  int2 xa;
+};
+template <int GS>
+FACO_DEV GroupStatic group_static(const Inst &I, int a, bool gvalid) {
+  const int K = I.k, s = lane_id() & (GS - 1);
+  const bool act = gvalid && s < K;
+  const size_t row = (size_t)a * (size_t)K;
+  GroupStatic P;
+  P.a = gvalid ? a : -1;
+  P.b = act ? I.cl[row + s] : a;
+  P.d_ab = act ? I.cl_d[row + s] : 0;
+  P.xa = I.xy[a];
+  return P;
+}
+
+// eval_group with the static loads in registers: the positions of a and of
+// its candidates are then the first level of loads, and the tour neighbours
+// of both the second.
+template <int GS>
+FACO_DEV GroupEval eval_group_pre(const Inst &I, uint32_t flags, int a, bool gvalid,
+                                  const GroupStatic &P, const int32_t *route,
+                                  const int32_t *pos, const int2 *rxy) {
+  const int n = I.n, K = I.k, lane = lane_id();
+  const int s = lane & (GS - 1);
+  const bool act = gvalid && s < K;
+  GroupEval R;
+  R.a = a;
+  const int b = P.b, d_ab = P.d_ab;
+  const int2 xa = P.xa;
+  // level 1
+  const int pa = pos[a];
+  const int pb = pos[b];
+  const int2 xb = I.xy[b];
+  // level 2
+  const int pn = wrapn(pa + s - 3, n);
+  const int nb = s < 7 ? route[pn] : a;
+  const int2 xnb = s < 7 ? rxy[pn] : xa;
+  const int pbs = pb + 1 == n ? 0 : pb + 1, pbp = pb == 0 ? n - 1 : pb - 1;
+  const int bs = route[pbs], bp = route[pbp];
+  const int2 xbs = rxy[pbs], xbp = rxy[pbp];
+  R.pa = pa; R.b = b; R.pb = pb; R.pbs = pbs; R.pbp = pbp; R.bs = bs; R.bp = bp;
+  R.nb = nb; R.xa = xa; R.xnb = xnb; R.xb = xb; R.xbs = xbs; R.xbp = xbp; R.d_ab = d_ab;
+  group_keys<GS>(flags, act, R);
+  return R;
+}
+
 // The part of a group evaluation after the loads: neighbourhood costs and
 // the 2-opt keys.
 template <int GS>
@@ -1712,6 +1764,13 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
   flags = (uint32_t)uniform_i((int)flags);
   int changes = 0, changes_at_sweep = -1;
   int64_t gain = 0;
+  // The next round's static loads (its groups' candidate rows and
+  // coordinates), issued during this round for the groups it will most
+  // likely hold; used if it holds them.
+  GroupStatic pre;
+  pre.a = -1;
+  pre.b = pre.d_ab = 0;
+  pre.xa = make_int2(0, 0);
   for (;;) {
     for (;;) {
       Q.count = uniform_i(Q.count);
@@ -1746,14 +1805,33 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
       const int64_t t0 = fine_ticks();
       SegEval Z;
       GroupEval R;
-      if constexpr (SEG)
+      if constexpr (SEG) {
         R = eval_group_seg<GS>(I, flags, a, grp < gcount, SQ.T, Z);
-      else
-        R = eval_group<GS>(I, flags, a, grp < gcount, route, pos, rxy);
+      } else {
+        // the prefetched loads serve if every group is full and holds the
+        // city they were loaded for
+        const bool hit = ballot(!(grp < gcount && pre.a == a)) == 0ull;
+        if (hit)
+          R = eval_group_pre<GS>(I, flags, a, true, pre, route, pos, rxy);
+        else
+          R = eval_group<GS>(I, flags, a, grp < gcount, route, pos, rxy);
+        pre.a = -1;
+      }
       // Or-opt is only tried where no 2-opt move exists, and only cities
       // before the first one with a 2-opt move can be the chosen one
       const uint64_t h2 = ballot((lane & (GS - 1)) == 0 && grp < gcount && R.key2 > 0);
       const int j2 = uniform_i(h2 ? ctz64(h2) / GS : gcount);
+      // Most likely the move is the first 2-opt one (j2) and the next round
+      // holds the G listed cities after it: load their static data now,
+      // beside the rest of this round (a wrong guess only costs the loads).
+      if constexpr (!SEG) {
+        const int np_guess = j2 < gcount ? j2 + 1 : gcount;
+        if (Q.in_lds && j2 < gcount && Q.count - np_guess >= G) {
+          int h = Q.head + np_guess + grp;
+          h = h >= Q.cap ? h - Q.cap : h;
+          pre = group_static<GS>(I, Q.lr[h], true);
+        }
+      }
       if (TW > 1 && (flags & LS_OROPT) && j2 > 0) {
         // the team's helpers evaluate the Or-opt variants from the leader's loads
         const int64_t to = fine_ticks();
