@@ -392,8 +392,13 @@ def full_run(F, I, torch, stream, w):
     g = F.faco_build_instance(xy, stream=stream, **w.params())
     F.faco_set_verify(g, True)
     F.faco_set_timing(g, True, reserve_iterations=w.iterations)
+    tk0 = F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS)
     total_ms = run_iterations_timed(F, g, stream, w.iterations, torch, "full run")
     phase_ms, launches = F.faco_phase_times(g)
+    per = (F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS) - tk0).astype(np.float64).mean(0) / w.iterations
+    per_ant_us = {name: round(float(per[i]) / 100.0, 1) for i, name in
+                  [(0, "construct"), (1, "ls_eval"), (2, "ls_apply"), (3, "sweep"),
+                   (4, "ant_total"), (15, "ls_rewrite")]}
     fault = F.faco_debug_get(g, F.FACO_DBG_FAULT)
     _, best_len = F.faco_get_best_tour(g) if fault[0] == 0 else (None, -1)
     info = F.faco_debug_get(g, F.FACO_DBG_INFO)
@@ -406,6 +411,7 @@ def full_run(F, I, torch, stream, w):
         "best_length": int(best_len),
         "lengths_verified": bool(fault[0] == 0 and fault[3] == w.iterations * (A + 1)),
         "tours_verified": int(fault[3]), "device_faults": int(fault[0]),
+        "per_ant_us": per_ant_us,
     }
 
 
