@@ -363,7 +363,7 @@ def slowest_ants(F, stream, w, warmup, steps, torch):
     F.faco_run_iterations(g, warmup)
     torch.cuda.synchronize()
     names = {0: "construct", 1: "ls_eval", 2: "ls_apply", 15: "ls_rewrite", 3: "sweep",
-             4: "ant_total"}
+             24: "sweep_tests", 25: "sweep_listing", 4: "ant_total"}
     prev = F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS).astype(np.int64)
     cprev = F.faco_debug_get(g, F.FACO_DBG_COUNTER_TOTALS).astype(np.int64)
     slow, med = [], []
@@ -377,6 +377,7 @@ def slowest_ants(F, stream, w, warmup, steps, torch):
         for a, out in ((order[-1], slow), (order[len(order) // 2], med)):
             row = {v: d[a, k] / 100.0 for k, v in names.items()}
             row["moves"] = dc[a, 6] + dc[a, 7]
+            row["sweep_cities"] = d[a, 26]
             row["moved_elems"] = dc[a, 8]
             out.append(row)
     g.close()
@@ -512,10 +513,11 @@ def main():
     tk_us = {name: round(float(per[i]) / 100.0, 1) for i, name in
              [(0, "construct"), (1, "ls_eval"), (2, "ls_apply"), (3, "sweep"), (4, "ant_total"),
               (8, "spec_windows"), (9, "one_steps"), (10, "copies"), (11, "fallbacks"),
-              (13, "ls_eval_oropt"), (15, "ls_rewrite")]}
+              (13, "ls_eval_oropt"), (15, "ls_rewrite"), (24, "sweep_tests"),
+              (25, "sweep_listing")]}
     tk_calls = {name: round(float(per[i]), 1) for i, name in
                 [(5, "spec_windows"), (6, "one_steps"), (7, "copies"), (12, "eval_rounds"),
-                 (14, "oropt_rounds")]}
+                 (14, "oropt_rounds"), (26, "sweep_cities")]}
     slowest_us = round(float(tk[:, 4].max()) / args.steps / 100.0, 1)
     dcnt = tot1 - tot0
     bytes_survey = float(survey_bytes_per_ant(dcnt, n, k).sum())

@@ -259,7 +259,7 @@ enum {
   FACO_DBG_INIT_COUNTERS = 10, /* int64 [FACO_NCNT] of the initial solution  */
   FACO_DBG_COUNTER_TOTALS = 11, /* int64 [n_ants][FACO_NCNT], summed over all
                                    iterations since the build                 */
-  FACO_DBG_PHASE_TICKS = 12, /* int64 [n_ants][24] summed since the build;
+  FACO_DBG_PHASE_TICKS = 12, /* int64 [n_ants][32] summed since the build;
                                device wall-clock ticks (100 MHz): [0]
                                construction, [1] move evaluation, [2] move
                                application, [3] sweeps, [4] whole ant, [8]
@@ -274,7 +274,10 @@ enum {
                                them, [18] cities relabelled by splits, [19]
                                splits, [20] records passed by moves, [21]
                                ticks of the leader's part of moves, [22]
-                               ticks of the team's part; [23] zero        */
+                               ticks of the team's part; sweeps: [24] ticks
+                               in the move tests, [25] ticks in listing the
+                               improvable cities, [26] cities tested;
+                               [23], [27..31] zero                       */
   FACO_DBG_TEAM_WAVES = 13, /* int32 [1]: waves per ant of this instance   */
   FACO_DBG_FAULT = 14,      /* int64 [4]: FACO_FAULT_* bits found on the
                                device, the first fault's ant (-1: initial

@@ -128,7 +128,7 @@ constexpr int kMaxCl = 32;
 constexpr int kMaxBl = 64;
 constexpr int kMaxOrSeg = 3;
 // tick and count slots per ant (FACO_DBG_PHASE_TICKS)
-constexpr int kTicks = 24;
+constexpr int kTicks = 32;
 // capacity of the segment record table of a segment-list tour
 constexpr int kSegCap = 2048;
 

@@ -1181,10 +1181,15 @@ FACO_DEV Move extract_move(const Inst &I, const GroupEval &R, int j) {
 // chunk is loaded, then tested), while a lane of the wave still needs them;
 // inside a chunk every array index is a compile-time constant, so nothing
 // is indexed at run time.
+// candidates per chunk of the sweep's test (4: the test stops sooner than
+// with 8, measured on the sweeps of the 100k workload; 16 at once spills)
+#ifndef FACO_SWEEP_CK
+#define FACO_SWEEP_CK 4
+#endif
 template <int KT>
 FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x,
                             const int32_t *route, const int32_t *pos, const int2 *rxy) {
-  constexpr int CK = KT < 8 ? KT : 8;
+  constexpr int CK = KT < FACO_SWEEP_CK ? KT : FACO_SWEEP_CK;
   const int n = I.n, K = I.k;
   const size_t row = (size_t)x * (size_t)K;
   // first chunk of the list with the city's own data
@@ -1587,23 +1592,32 @@ FACO_DEV void sweep_part(const Inst &I, uint32_t flags, int count, int w, TeamLd
   }
 }
 
+// Sweep tick slots (per ant): ticks in the move tests, ticks in listing the
+// improvable cities, cities tested.
+enum { TK_SWEEP_TESTS = 24, TK_SWEEP_LIST = 25, TK_SWEEP_CITIES = 26 };
+
 template <int KT, int TW, class TT>
 FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q, const TT &T,
-                   uint32_t *inq, uint32_t *touched, uint32_t *ord, TeamLds *tl) {
+                   uint32_t *inq, uint32_t *touched, uint32_t *ord, TeamLds *tl,
+                   LaneCounters &tk) {
   const int lane = lane_id();
   int bx = -1, bcount = 0;
   auto test = [&](int cnt) {
+    const int64_t t0 = fine_ticks();
+    tk[TK_SWEEP_CITIES] += cnt;
     if (TW == 1) {
       if (lane < cnt) {
         const int ox = I.orig_of[bx];
         if (has_improving<KT>(I, flags, bx, T)) bit_set(ord, ox);
       }
+      tk[TK_SWEEP_TESTS] += fine_ticks() - t0;
       return;
     }
     // cnt cities sit in tl->cities[0..cnt)
     team_post(tl, OP_SWEEP, cnt, (int)flags);
     sweep_part<KT, TW>(I, flags, cnt, 0, tl, ord, T);
     team_sync();
+    tk[TK_SWEEP_TESTS] += fine_ticks() - t0;
   };
   if (TW == 1) {
     for (int w0 = 0; w0 < W; w0 += kWave) {
@@ -1653,6 +1667,7 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q, const TT &T,
     if (fill) test(fill);
   }
   wave_fence();
+  const int64_t tl0 = fine_ticks();
   // list the marked cities, ascending original number, 64 at a time
   int pushed = 0, bo = -1;
   bcount = 0;
@@ -1681,6 +1696,7 @@ FACO_DEV int sweep(const Inst &I, uint32_t flags, int W, Queue &Q, const TT &T,
     }
   }
   if (bcount) list(bcount);
+  tk[TK_SWEEP_LIST] += fine_ticks() - tl0;
   return pushed;
 }
 
@@ -1919,10 +1935,10 @@ FACO_DEV int64_t local_search(const Inst &I, uint32_t flags, int32_t *route,
     const int64_t t2 = ticks();
     int pushed;
     if constexpr (SEG)
-      pushed = uniform_i(sweep<KT, TW>(I, flags, W, Q, SQ.T, inq, touched, ord, tl));
+      pushed = uniform_i(sweep<KT, TW>(I, flags, W, Q, SQ.T, inq, touched, ord, tl, tk));
     else
       pushed = uniform_i(sweep<KT, TW>(I, flags, W, Q, FlatT{route, pos, rxy}, inq, touched,
-                                       ord, tl));
+                                       ord, tl, tk));
     tk[3] += ticks() - t2;
     if (pushed == 0) break;
   }

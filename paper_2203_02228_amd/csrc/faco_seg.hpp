@@ -217,7 +217,7 @@ FACO_DEV void sg_nbhd7(const int4 *rec, int g, int4 r, int o, int n, int *sx) {
 // has_improving on a segment-list tour (the sweep's test, one city per lane).
 template <int KT>
 FACO_DEV bool has_improving(const Inst &I, uint32_t flags, int x, const SegT &T) {
-  constexpr int CK = KT < 8 ? KT : 8;
+  constexpr int CK = KT < FACO_SWEEP_CK ? KT : FACO_SWEEP_CK;
   const int n = I.n, K = I.k;
   const size_t row = (size_t)x * (size_t)K;
   int cb[CK], cd[CK];
