@@ -355,6 +355,19 @@ def run_iterations_timed(F, g, stream, steps, torch, label):
     return ev0.elapsed_time(ev1)
 
 
+def window_without_events(F, stream, w, warmup, steps, torch):
+    """The timed window again on a fresh build with the per-launch HIP events
+    off (the headline keeps them on: the roofline takes the ant kernel's mean
+    launch time from them), to show what they cost."""
+    g = F.faco_build_instance(w.points(), stream=stream, **w.params())
+    F.faco_run_iterations(g, warmup)
+    torch.cuda.synchronize()
+    ms = run_iterations_timed(F, g, stream, steps, torch, "window without launch events")
+    g.close()
+    return {"value": round(w.n_ants * steps / (ms * 1e-3), 2),
+            "ms_per_step": round(ms / steps, 4)}
+
+
 def slowest_ants(F, stream, w, warmup, steps, torch):
     """The same window on a fresh build, one iteration at a time: the phase
     times of each iteration's slowest ant (it sets the launch time), averaged
@@ -602,6 +615,8 @@ def main():
         out["full_run"] = full_run(F, I, torch, stream, w)
         log(f"full run: {out['full_run']}")
     if not args.no_slowest:
+        out["window_without_launch_events"] = window_without_events(F, stream, w, args.warmup,
+                                                                    args.steps, torch)
         log("slowest ant of each iteration over the same window (fresh build) ...")
         out["ants_by_iteration_us"] = slowest_ants(F, stream, w, args.warmup, args.steps, torch)
     if not args.no_cpu_baseline:

@@ -147,3 +147,36 @@ def test_segment_setting_errors():
     g = F.faco_build_instance(I.make_points("uniform", 100, 1), n_ants=4)
     assert np.array_equal(F.faco_debug_get(g, F.FACO_DBG_TOUR), [0, 0, 0])
     g.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name,iters", [("uniform1k", 200), ("gmm20k", 100), ("stipple100k", 30)])
+def test_segments_configured_workloads(name, iters):
+    """The configured workloads with segment lists (team size and segment
+    length by size), against the oracle: lengths, counters, state, limits and
+    source every iteration; routes, pheromone and the best tour every 10th and
+    at the end; at 100k the device also recomputes every tour length."""
+    from tests.test_gpu_configs import HOST_THREADS, _cmp_heavy, _cmp_light
+    from oracle import oracle as O
+    w = I.WORKLOADS[name]
+    xy = w.points()
+    say(f"[gpu] segments {name}: n={w.n} iterations={iters}")
+    o = O.Oracle(xy, threads=HOST_THREADS, **w.params())
+    F.faco_set_tour_segments(2, 0, 0)
+    try:
+        g = F.faco_build_instance(xy, **w.params())
+    finally:
+        F.faco_set_tour_segments(0, 0, 0)
+    assert F.faco_debug_get(g, F.FACO_DBG_TOUR)[0] == 1
+    F.faco_set_verify(g, name == "stipple100k")
+    _cmp_setup(o, g)
+    for it in range(1, iters + 1):
+        F.faco_run_iterations(g, 1)
+        o.run(1)
+        _cmp_light(o, g, it)
+        if it % 10 == 0 or it == iters:
+            _cmp_heavy(o, g, it)
+    tk = F.faco_debug_get(g, F.FACO_DBG_PHASE_TICKS)
+    assert tk[:, 19].sum() > 0  # moves split records
+    g.close()
+    o.close()
