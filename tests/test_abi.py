@@ -41,3 +41,27 @@ def test_footprint_is_pure_arithmetic():
     # coords + cl/eta/tau + backup + source/gbest + ant arrays
     assert b >= 8 * 200000 + 12 * 200000 * 16 + 4 * 200000 * 64 + 12 * 200000 + 12 * 200000 * 32
     assert F.faco_footprint_bytes(3, p) == 0
+
+
+def test_tour_segment_setting_checked_on_the_host():
+    """faco_set_tour_segments validates its arguments and, with segment lists
+    asked for, the footprint of a build grows by the second array buffer and
+    the per-city record labels (24 n bytes per ant); flat arrays are the
+    default (host arithmetic only)."""
+    if not os.path.exists(F.LIB_PATH):
+        pytest.skip("HIP library not built")
+    for args in [(3, 0, 0), (-1, 0, 0), (2, 25, 0), (2, -1, 0), (2, 0, 7), (2, 0, 2049)]:
+        with pytest.raises(F.FacoError) as e:
+            F.faco_set_tour_segments(*args)
+        assert e.value.code == F.FACO_EINVAL
+    p = F.make_params(n_ants=16, cl_size=16, bl_size=64)
+    n = 100000
+    flat = F.faco_footprint_bytes(n, p)
+    F.faco_set_tour_segments(2, 0, 0)
+    try:
+        seg = F.faco_footprint_bytes(n, p)
+    finally:
+        F.faco_set_tour_segments(0, 0, 0)
+    assert seg - flat >= 24 * n * 16
+    assert seg - flat < 24 * n * 16 + 16 * 4096
+    assert F.faco_footprint_bytes(n, p) == flat
