@@ -261,7 +261,9 @@ def run_served_mode(args):
     pts = gen_points_parallel([(w.kind, w.n, w.instance_seed) for _, w in reqs])
     log(f"served: {count} request point sets in {time.time() - t0:.0f} s")
     torch.cuda.set_device(0)
-    srv = S.Server(hbm_budget_bytes=args.hbm_budget << 30, chunk=args.chunk)
+    classes = tuple(int(x) for x in args.served_classes.split(",")) + (1 << 30,)
+    srv = S.Server(hbm_budget_bytes=args.hbm_budget << 30, chunk=args.chunk, classes=classes,
+                   builders=args.served_builders)
     tuned, tune_s = {}, 0.0
     if args.serve_tune:
         # before the stream: a few requests of each size class, built aside
@@ -334,6 +336,13 @@ def run_served_mode(args):
         "n_range": [min(w.n for _, w in reqs), max(w.n for _, w in reqs)],
         "errors": len(srv.errors),
         "latency_stages_s": stages,
+        # per size class: resident solves per batch call and time per iteration
+        "classes": [{"n_below": hi, "calls": st["calls"],
+                     "mean_resident": round(st["active_sum"] / max(1, st["calls"]), 2),
+                     "max_resident": st["max_active"],
+                     "ms_per_iteration": round(1e3 * st["busy_s"] / max(1, st["iterations"]), 2),
+                     "busy_frac": round(st["busy_s"] / makespan, 3)}
+                    for hi, st in zip(srv.classes, srv.class_stats)],
         "tuned_by_class": {str(k): v for k, v in tuned.items()}, "autotune_s": round(tune_s, 1),
     }
 
@@ -454,6 +463,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB for resident solves")
     ap.add_argument("--seq-sample", type=int, default=16)
+    ap.add_argument("--served-classes", default="8000,40000",
+                    help="upper size bounds of the served size classes but the last")
+    ap.add_argument("--served-builders", type=int, default=2)
     ap.add_argument("--serve-tune", type=int, default=1)
     ap.add_argument("--serve-tune-samples", type=int, default=8,
                     help="requests per size class the served autotune times")

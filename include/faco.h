@@ -109,8 +109,25 @@ int faco_run_iterations(faco_instance *h, int32_t iterations);
 int faco_get_best_tour(faco_instance *h, int32_t *tour_out,
                        int64_t *length_out);
 
-/* Free all device state of the handle.  NULL is allowed. */
+/*
+ * Release all device state of the handle.  NULL is allowed.  Waits for the
+ * handle's stream; the device blocks then go to a per-device cache of the
+ * library (at most 32 GiB; beyond it they are freed) and later builds and
+ * batch tables reuse them, because hipFree would wait for all work queued on
+ * the device, every other stream's included.
+ */
 void faco_destroy_instance(faco_instance *h);
+
+/*
+ * Move the handle to another stream: later calls on it (iterations, batch
+ * ordering, reads, destroy) run on and wait for `hip_stream` (NULL = the
+ * default stream), after the handle's work already queued on its previous
+ * stream.  A server that builds on a builder stream and then runs a solve on
+ * its batch stream moves it there, so that the solve's batches and reads
+ * never wait for other builds queued later on the builder stream.
+ * Errors: FACO_EINVAL (NULL handle), FACO_EDEVICE.
+ */
+int faco_set_stream(faco_instance *h, void *hip_stream);
 
 /* Last error message of the handle, or of the calling thread if h is NULL.
  * The string stays valid until the next call on the same handle/thread. */

@@ -33,7 +33,7 @@ struct faco_instance {
   int32_t n = 0, k = 0, bl = 0;
   hipStream_t stream = nullptr;
   Inst dv{};
-  std::vector<void *> allocs;
+  std::vector<std::pair<void *, size_t>> allocs;  // device blocks and their sizes
   std::string err;
   size_t lds_ant = 0;   // LDS of the per-iteration ant kernel
   size_t lds_init = 0;  // LDS of the initial solution's ant kernel (flat tour)
@@ -101,17 +101,101 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // in progress on another thread.
 static std::mutex g_capture_mu;
 
-static int dalloc(faco_instance *h, void **ptr, size_t bytes) {
+// Device blocks released by destroyed instances and outgrown batch tables,
+// kept per device for later allocations.  hipFree waits for all work queued
+// on the device: in a serving loop every retirement would stall the other
+// streams' solves and leave the GPU idle while it drained.  A block enters
+// the cache only once no queued work can still touch it; sizes are rounded
+// to eighths of their leading power of two so that blocks fit later requests
+// of similar size.
+static std::mutex g_blk_mu;
+static std::map<int, std::multimap<size_t, void *>> g_blk_free;
+static size_t g_blk_cached = 0;
+static const size_t kBlkCacheLimit = (size_t)32 << 30;
+
+static size_t blk_round(size_t b) {
+  if (b <= 256) return 256;
+  const int e = 63 - __builtin_clzll((unsigned long long)b);
+  const size_t step = (size_t)1 << (e - 3);
+  return (b + step - 1) / step * step;
+}
+
+// Free every cached block of `dev` (waits for the device's queued work).
+static void blk_trim(int dev) {
+  std::vector<void *> out;
+  {
+    std::lock_guard<std::mutex> lk(g_blk_mu);
+    auto &m = g_blk_free[dev];
+    for (auto &kv : m) {
+      out.push_back(kv.second);
+      g_blk_cached -= kv.first;
+    }
+    m.clear();
+  }
+  std::lock_guard<std::mutex> lk(g_capture_mu);
+  for (void *q : out) (void)hipFree(q);
+}
+
+// A block of at least `bytes` on the current device `dev`: a cached one of
+// at most 5/4 the rounded size, else a new allocation (after one trim of the
+// cache if the device is out of memory).  *got receives the block's size.
+static hipError_t blk_get(int dev, size_t bytes, void **ptr, size_t *got) {
+  const size_t want = blk_round(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_blk_mu);
+    auto &m = g_blk_free[dev];
+    auto it = m.lower_bound(want);
+    if (it != m.end() && it->first <= want + want / 4) {
+      *ptr = it->second;
+      *got = it->first;
+      g_blk_cached -= it->first;
+      m.erase(it);
+      return hipSuccess;
+    }
+  }
   hipError_t e;
   {
     std::lock_guard<std::mutex> lk(g_capture_mu);
-    e = hipMalloc(ptr, bytes ? bytes : 4);
+    e = hipMalloc(ptr, want);
   }
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    blk_trim(dev);
+    std::lock_guard<std::mutex> lk(g_capture_mu);
+    e = hipMalloc(ptr, want);
+  }
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return e;
+  }
+  *got = want;
+  return hipSuccess;
+}
+
+// Return a block that no queued work uses any more; beyond the cache's limit
+// it is freed instead.
+static void blk_put(int dev, void *p, size_t bytes) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_blk_mu);
+    if (g_blk_cached + bytes <= kBlkCacheLimit) {
+      g_blk_free[dev].emplace(bytes, p);
+      g_blk_cached += bytes;
+      return;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_capture_mu);
+  (void)hipFree(p);
+}
+
+static int dalloc(faco_instance *h, void **ptr, size_t bytes) {
+  size_t got = 0;
+  const hipError_t e = blk_get(h->device, bytes ? bytes : 4, ptr, &got);
   if (e != hipSuccess) {
     *ptr = nullptr;
     return set_err(h, FACO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
-  h->allocs.push_back(*ptr);
+  h->allocs.emplace_back(*ptr, got);
   return FACO_OK;
 }
 
@@ -622,17 +706,35 @@ extern "C" int faco_get_best_tour(faco_instance *h, int32_t *tour_out, int64_t *
 
 extern "C" void faco_destroy_instance(faco_instance *h) {
   if (!h) return;
-  (void)hipStreamSynchronize(h->stream);
+  // every batch that used the instance is ordered before its stream's later
+  // work, so after this wait no queued work touches its blocks
+  const bool idle = hipStreamSynchronize(h->stream) == hipSuccess;
   for (auto &tl : h->pending) {
     (void)hipEventDestroy(tl.a);
     (void)hipEventDestroy(tl.b);
   }
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-  {
+  if (idle) {
+    for (auto &a : h->allocs) blk_put(h->device, a.first, a.second);
+  } else {
     std::lock_guard<std::mutex> lk(g_capture_mu);
-    for (void *p : h->allocs) (void)hipFree(p);
+    for (auto &a : h->allocs) (void)hipFree(a.first);
   }
   delete h;
+}
+
+extern "C" int faco_set_stream(faco_instance *h, void *hip_stream) {
+  if (!h) return set_err(nullptr, FACO_EINVAL, "handle is NULL");
+  const hipStream_t ns = (hipStream_t)hip_stream;
+  if (ns == h->stream) return FACO_OK;
+  hipEvent_t ev;
+  HIP_TRY(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  hipError_t e = hipEventRecord(ev, h->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ns, ev, 0);
+  (void)hipEventDestroy(ev);
+  HIP_TRY(h, e);
+  h->stream = ns;
+  return FACO_OK;
 }
 
 extern "C" const char *faco_last_error(const faco_instance *h) {
@@ -806,6 +908,7 @@ struct BatchWs {
   faco::BatchRun *run = nullptr;
   size_t cap_insts = 0, cap_amap = 0, cap_ctl = 0;
   hipEvent_t last_done = nullptr;  // completion of the previous batch
+  hipStream_t cap = nullptr;       // the stream the batch iteration is captured on
 };
 // one workspace per stream, so batches on different streams run concurrently
 static std::map<hipStream_t, BatchWs> g_ws_map;
@@ -960,15 +1063,22 @@ static void enqueue_batch_iteration(const BatchShape &B, const Inst *d_insts,
   hipLaunchKernelGGL(faco::pheromone_batch_kernel, g_tau, dim3(256), 0, s, d_insts);
 }
 
-// Grow a workspace array (the previous batch on the stream has finished).
+// Grow a workspace array (the previous batch on the stream has finished, so
+// the old block goes back to the cache) to at least twice its size.
 template <class T>
-static hipError_t ws_grow(T *&ptr, size_t &cap, size_t want) {
+static hipError_t ws_grow(int dev, T *&ptr, size_t &cap, size_t want) {
   if (cap >= want) return hipSuccess;
-  if (ptr) (void)hipFree(ptr);
+  if (want < 2 * cap) want = 2 * cap;
+  blk_put(dev, ptr, sizeof(T) * cap);  // at most the block's true size
   ptr = nullptr;
   cap = 0;
-  const hipError_t e = hipMalloc((void **)&ptr, sizeof(T) * want);
-  if (e == hipSuccess) cap = want;
+  void *q = nullptr;
+  size_t got = 0;
+  const hipError_t e = blk_get(dev, sizeof(T) * want, &q, &got);
+  if (e == hipSuccess) {
+    ptr = (T *)q;
+    cap = got / sizeof(T);
+  }
   return e;
 }
 
@@ -997,12 +1107,14 @@ static int run_batch_one(faco_instance *const *hs, int32_t count, int32_t iterat
   if (grow) BT(hipEventSynchronize(g_ws.last_done));
   BT(hipStreamWaitEvent(st, g_ws.last_done, 0));
   // device tables
-  {
-    std::lock_guard<std::mutex> alloc_lk(g_capture_mu);
-    BT(ws_grow(g_ws.insts, g_ws.cap_insts, (size_t)count));
-    BT(ws_grow(g_ws.amap, g_ws.cap_amap, (size_t)total));
-    BT(ws_grow(g_ws.ctl, g_ws.cap_ctl, (size_t)count));
-    if (!g_ws.run) BT(hipMalloc((void **)&g_ws.run, sizeof(faco::BatchRun)));
+  if (grow) {
+    int dev = 0;
+    BT(hipGetDevice(&dev));
+    BT(ws_grow(dev, g_ws.insts, g_ws.cap_insts, (size_t)count));
+    BT(ws_grow(dev, g_ws.amap, g_ws.cap_amap, (size_t)total));
+    BT(ws_grow(dev, g_ws.ctl, g_ws.cap_ctl, (size_t)count));
+    size_t cap_run = 0;
+    if (!g_ws.run) BT(ws_grow(dev, g_ws.run, cap_run, 1));
   }
   // order after the handles' own streams
   for (int32_t i = 0; i < count && handles; ++i) {
@@ -1058,8 +1170,8 @@ static int run_batch_one(faco_instance *const *hs, int32_t count, int32_t iterat
       BT(hipGetLastError());
     } else {
       // one iteration captured as a graph, replayed
-      hipStream_t cap;
-      BT(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      if (!g_ws.cap) BT(hipStreamCreateWithFlags(&g_ws.cap, hipStreamNonBlocking));
+      hipStream_t cap = g_ws.cap;
       hipGraph_t graph;
       hipGraphExec_t exec;
       {
@@ -1072,7 +1184,6 @@ static int run_batch_one(faco_instance *const *hs, int32_t count, int32_t iterat
       for (int32_t it = 0; it < iterations; ++it) BT(hipGraphLaunch(exec, st));
       BT(hipGraphExecDestroy(exec));
       BT(hipGraphDestroy(graph));
-      BT(hipStreamDestroy(cap));
     }
   }
   // later calls on each handle's stream, and the next batch, come after this one

@@ -33,7 +33,7 @@ EXPORTED = ["faco_build_instance", "faco_run_iterations", "faco_get_best_tour",
             "faco_phase_times", "faco_set_batch_ants_per_block", "faco_set_team_waves",
             "faco_set_queue_lds_capacity", "faco_set_verify", "faco_run_batch_noalloc",
             "faco_set_batch_config", "faco_get_batch_config", "faco_autotune_batch",
-            "faco_set_tour_segments"]
+            "faco_set_tour_segments", "faco_set_stream"]
 
 
 class faco_params(ctypes.Structure):
@@ -88,6 +88,8 @@ def lib():
         L.faco_get_best_tour.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int64)]
         L.faco_destroy_instance.restype = None
         L.faco_destroy_instance.argtypes = [vp]
+        L.faco_set_stream.restype = ctypes.c_int
+        L.faco_set_stream.argtypes = [vp, vp]
         L.faco_last_error.restype = ctypes.c_char_p
         L.faco_last_error.argtypes = [vp]
         L.faco_run_batch.restype = ctypes.c_int
@@ -194,6 +196,13 @@ def faco_destroy_instance(inst):
     if inst.h:
         lib().faco_destroy_instance(inst.h)
         inst.h = None
+
+
+def faco_set_stream(inst, stream):
+    """Later calls on the handle run on `stream`, after its queued work."""
+    if inst.h is None:
+        raise FacoError(FACO_EINVAL, "handle is closed")
+    _check(lib().faco_set_stream(inst.h, _stream_handle(stream)), inst.h)
 
 
 def faco_run_batch(insts, iterations, stream=None):

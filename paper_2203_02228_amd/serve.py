@@ -3,8 +3,9 @@
 Requests (points + parameters + an iteration budget) arrive at any time.  A
 request is admitted when its device footprint (faco_footprint_bytes: points,
 candidate/backup lists, pheromone, tours) fits in the HBM budget next to the
-solves already resident; it is then built on a builder stream and joins the
-running batch of its size class at the next batch call.  Each size class has a
+solves already resident; it is then built on a builder stream, moved to the
+stream of its size class and joins the running batch of that class at the
+next batch call.  Each size class has a
 worker with its own stream that advances all of its resident solves together
 (faco_run_batch, one launch per phase) in chunks of iterations, retires the
 ones that reached their budget and admits newly built ones between chunks.
@@ -59,6 +60,10 @@ class Server:
         self.completed = []
         self.errors = []
         self.tuned = {}
+        # per size class: batch calls, iterations, resident solves summed over
+        # calls, the most resident at once, and host time inside batch calls
+        self.class_stats = [dict(calls=0, iterations=0, active_sum=0, max_active=0, busy_s=0.0)
+                            for _ in self.classes]
         F.faco_set_batch_ants_per_block(ants_per_block)
         self.build_streams = [torch.cuda.Stream() for _ in range(builders)]
         self.run_streams = [torch.cuda.Stream() for _ in self.classes]
@@ -160,6 +165,9 @@ class Server:
                 r = self.build_q.popleft()
             try:
                 r.handle = F.faco_build_instance(r.xy, stream=stream, **r.params)
+                # the solve now lives on its class's stream: its batches and
+                # reads must not wait for the next builds on this stream
+                F.faco_set_stream(r.handle, self.run_streams[self._class_of(len(r.xy))])
                 r.built = time.perf_counter()
                 with self.lock:
                     self.ready[self._class_of(len(r.xy))].append(r)
@@ -208,8 +216,15 @@ class Server:
                     active.append(self.ready[c].popleft())
             try:
                 steps = min(self.chunk, min(r.iterations - r.done_iters for r in active))
+                t0 = time.perf_counter()
                 F.faco_run_batch([r.handle for r in active], steps, stream=stream)
                 stream.synchronize()
+                st = self.class_stats[c]
+                st["calls"] += 1
+                st["iterations"] += steps
+                st["active_sum"] += len(active)
+                st["max_active"] = max(st["max_active"], len(active))
+                st["busy_s"] += time.perf_counter() - t0
             except Exception as e:
                 # every resident solve of the class fails with the batch
                 for r in active:

@@ -65,3 +65,10 @@ def test_tour_segment_setting_checked_on_the_host():
     assert seg - flat >= 24 * n * 16
     assert seg - flat < 24 * n * 16 + 16 * 4096
     assert F.faco_footprint_bytes(n, p) == flat
+
+
+def test_set_stream_rejects_null_handle():
+    """faco_set_stream checks its handle on the host (no GPU needed)."""
+    if not os.path.exists(F.LIB_PATH):
+        pytest.skip("HIP library not built")
+    assert F.lib().faco_set_stream(None, None) == F.FACO_EINVAL

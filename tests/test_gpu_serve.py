@@ -100,3 +100,33 @@ def test_capture_alongside_other_threads():
     for g in batch:
         g.close()
     assert not errors, errors[:3]
+
+
+def test_moved_handle_equals_unmoved():
+    """faco_set_stream: a handle moved between streams (after a few
+    iterations, then batched on a third stream, then read and destroyed on its
+    new stream) ends exactly where a handle that stayed on its build stream
+    ends; destroyed handles' device blocks are reused by the next builds."""
+    import torch
+    torch.cuda.set_device(0)
+    sa, sb, sc = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    xy = I.make_points("stipple", 3000, 77)
+    p = dict(n_ants=12, min_new_edges=8, rho=0.5, seed=5)
+    say("[gpu] set_stream: build two handles of n=3000")
+    for rep in range(2):
+        g0 = F.faco_build_instance(xy, stream=sa, **p)
+        g1 = F.faco_build_instance(xy, stream=sa, **p)
+        F.faco_run_iterations(g0, 4)
+        F.faco_run_iterations(g1, 4)
+        F.faco_set_stream(g1, sb)
+        F.faco_run_iterations(g0, 3)
+        F.faco_run_iterations(g1, 3)
+        F.faco_run_batch([g0], 2, stream=sc)
+        F.faco_run_batch([g1], 2, stream=sc)
+        t0, L0 = F.faco_get_best_tour(g0)
+        t1, L1 = F.faco_get_best_tour(g1)
+        assert L0 == L1 and np.array_equal(t0, t1)
+        for what in (F.FACO_DBG_PHEROMONE, F.FACO_DBG_ANT_ROUTES):
+            assert np.array_equal(F.faco_debug_get(g0, what), F.faco_debug_get(g1, what))
+        g0.close()
+        g1.close()

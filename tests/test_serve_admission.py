@@ -31,7 +31,13 @@ def _fake_modules(monkeypatch, log):
     monkeypatch.setattr(F, "faco_set_batch_ants_per_block", lambda apb: None)
     monkeypatch.setattr(F, "faco_build_instance", lambda xy, stream=None, **kw: H(len(xy)))
 
+    def set_stream(h, st):
+        h.stream = st
+    monkeypatch.setattr(F, "faco_set_stream", set_stream)
+
     def run_batch(hs, steps, stream=None):
+        # a resident solve runs on its class's stream, not its builder's
+        assert all(getattr(h, "stream", None) is stream for h in hs)
         log.append(("batch", sorted(h.n for h in hs), steps))
         for h in hs:
             h.it += steps
