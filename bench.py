@@ -35,6 +35,14 @@ import time
 
 import numpy as np
 
+# The served stream runs two builder streams and three size-class streams
+# beside the library's own.  HIP maps a process's streams onto
+# GPU_MAX_HW_QUEUES hardware queues (4 unless set) and work on streams that
+# share a queue runs in submission order: a class's batches then wait behind
+# another stream's build kernels (up to seconds for a 200k-city initial
+# solution).  HIP reads the setting once, when it initialises.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 

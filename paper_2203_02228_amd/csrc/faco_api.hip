@@ -200,8 +200,7 @@ static int dalloc(faco_instance *h, void **ptr, size_t bytes) {
 }
 
 static size_t knn_lds_bytes(int K, int BL) {
-  return (sizeof(int2) + sizeof(int32_t)) * faco::kKnnTile +
-         (sizeof(double) + sizeof(int32_t)) * (size_t)(K + BL) * 64;
+  return (sizeof(double) + sizeof(int32_t)) * (size_t)(K + BL) * 64;
 }
 
 static hipEvent_t take_event(faco_instance *h) {
@@ -605,7 +604,8 @@ extern "C" int faco_build_instance(const int32_t *xy, int32_t n, const faco_para
   BTRY(hipFuncSetAttribute((const void *)faco::knn_kernel,
                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)klds));
   hipLaunchKernelGGL(faco::knn_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), klds,
-                     h->stream, I.xy, I.orig_of, I.int_of, n, h->k, h->bl, (int32_t *)I.cl,
+                     h->stream, I.xy, I.orig_of, I.int_of, I.wbox, n, h->k, h->bl,
+                     (int32_t *)I.cl,
                      (int32_t *)I.bll,
                      (float *)I.eta, (int32_t *)I.cl_d, I.st);
   BTRY(hipGetLastError());

@@ -142,58 +142,76 @@ __global__ void __launch_bounds__(kVerifyBlock) verify_finish_batch_kernel(const
 
 // ===================================================================== //
 // Candidate + backup lists (Sec. 4.1): the K + BL nearest cities by
-// (squared distance, original number); eta = 1/d.  One query city per lane; candidate
-// cities stream through LDS in tiles; each lane keeps its sorted list in LDS.
+// (squared distance, original number); eta = 1/d.  One query city per lane
+// (64 consecutive labels per workgroup); each lane keeps its list sorted in
+// LDS.  Labels follow the Hilbert curve, so each run of 32 labels is a
+// compact box (wbox).  The wave visits the runs outward from its own in label
+// order (near cities first, so the lists fill with close cities early) and
+// skips a run when every lane's list is full and the run's box lies strictly
+// farther than the lane's last kept entry.  A skipped run holds no city that
+// could enter a list (a tie at the last entry's distance is still examined),
+// and the kept set does not depend on the visiting order: the lists are
+// exactly those of a scan over all cities.
 // ===================================================================== //
-constexpr int kKnnTile = 256;
+constexpr int kKnnRun = 32;
 
 __global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, const int32_t *orig_of,
-                                                 const int32_t *int_of, int n,
-                                                 int K, int BL, int32_t *cl, int32_t *bll,
-                                                 float *eta, int32_t *cl_d, DevState *st) {
+                                                 const int32_t *int_of, const int4 *wbox,
+                                                 int n, int K, int BL, int32_t *cl,
+                                                 int32_t *bll, float *eta, int32_t *cl_d,
+                                                 DevState *st) {
   extern __shared__ unsigned char knn_lds[];
   const int KK = K + BL;
   const int tid = threadIdx.x;
-  int2 *tile = reinterpret_cast<int2 *>(knn_lds);
-  int32_t *tile_o = reinterpret_cast<int32_t *>(knn_lds + sizeof(int2) * kKnnTile);
-  double *kd = reinterpret_cast<double *>(knn_lds + (sizeof(int2) + sizeof(int32_t)) * kKnnTile);
-  int32_t *ko = reinterpret_cast<int32_t *>(knn_lds + (sizeof(int2) + sizeof(int32_t)) * kKnnTile +
-                                            sizeof(double) * (size_t)KK * 64);
+  double *kd = reinterpret_cast<double *>(knn_lds);
+  int32_t *ko = reinterpret_cast<int32_t *>(knn_lds + sizeof(double) * (size_t)KK * 64);
   const int i = blockIdx.x * 64 + tid;
   const bool valid = i < n;
   const int2 xi = valid ? xy[i] : make_int2(0, 0);
   const int oi = valid ? orig_of[i] : -1;
+  const int nrun = (n + kKnnRun - 1) / kKnnRun;
+  const int c0 = (blockIdx.x * 64) / kKnnRun;
+  const int reach = c0 > nrun - 1 - c0 ? c0 : nrun - 1 - c0;
   int cnt = 0;
   double worst = 0.0;
   int worst_o = 0;
-  for (int t0 = 0; t0 < n; t0 += kKnnTile) {
-    __syncthreads();
-    for (int j = tid; j < kKnnTile; j += 64)
-      if (t0 + j < n) {
-        tile[j] = xy[t0 + j];
-        tile_o[j] = orig_of[t0 + j];
+  for (int d = 0; d <= reach; ++d) {
+    for (int side = 0; side < 2; ++side) {
+      if (d == 0 && side == 1) break;
+      const int c = side == 0 ? c0 + d : c0 - d;
+      if (c < 0 || c >= nrun) continue;
+      // does any lane still need this run?
+      bool need = valid;
+      if (valid && cnt == KK) {
+        const int4 b = wbox[c];
+        const int dx = max(max(b.x - xi.x, xi.x - b.z), 0);
+        const int dy = max(max(b.y - xi.y, xi.y - b.w), 0);
+        const double bd = (double)dx * (double)dx + (double)dy * (double)dy;
+        need = !(bd > worst);
       }
-    __syncthreads();
-    const int tn = min(kKnnTile, n - t0);
-    if (!valid) continue;
-    for (int jj = 0; jj < tn; ++jj) {
-      const int oj = tile_o[jj];
-      if (oj == oi) continue;
-      const double d = sqd(xi, tile[jj]);
-      // the list is sorted by (squared distance, original number)
-      if (cnt == KK && !(d < worst || (d == worst && oj < worst_o))) continue;
-      int q = cnt < KK ? cnt++ : KK - 1;
-      while (q > 0 && (kd[(q - 1) * 64 + tid] > d ||
-                       (kd[(q - 1) * 64 + tid] == d && ko[(q - 1) * 64 + tid] > oj))) {
-        kd[q * 64 + tid] = kd[(q - 1) * 64 + tid];
-        ko[q * 64 + tid] = ko[(q - 1) * 64 + tid];
-        --q;
-      }
-      kd[q * 64 + tid] = d;
-      ko[q * 64 + tid] = oj;
-      if (cnt == KK) {
-        worst = kd[(KK - 1) * 64 + tid];
-        worst_o = ko[(KK - 1) * 64 + tid];
+      if (!__any(need)) continue;
+      const int base = c * kKnnRun;
+      const int tn = min(kKnnRun, n - base);
+      if (!need) continue;
+      for (int jj = 0; jj < tn; ++jj) {
+        const int oj = orig_of[base + jj];
+        if (oj == oi) continue;
+        const double dd = sqd(xi, xy[base + jj]);
+        // the list is sorted by (squared distance, original number)
+        if (cnt == KK && !(dd < worst || (dd == worst && oj < worst_o))) continue;
+        int q = cnt < KK ? cnt++ : KK - 1;
+        while (q > 0 && (kd[(q - 1) * 64 + tid] > dd ||
+                         (kd[(q - 1) * 64 + tid] == dd && ko[(q - 1) * 64 + tid] > oj))) {
+          kd[q * 64 + tid] = kd[(q - 1) * 64 + tid];
+          ko[q * 64 + tid] = ko[(q - 1) * 64 + tid];
+          --q;
+        }
+        kd[q * 64 + tid] = dd;
+        ko[q * 64 + tid] = oj;
+        if (cnt == KK) {
+          worst = kd[(KK - 1) * 64 + tid];
+          worst_o = ko[(KK - 1) * 64 + tid];
+        }
       }
     }
   }

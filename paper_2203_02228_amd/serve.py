@@ -12,11 +12,19 @@ ones that reached their budget and admits newly built ones between chunks.
 State stays on the device from build to retirement.  The method's arithmetic
 is unchanged: a solve returns exactly what a lone faco_run_iterations run of
 the same request returns.
+
+The builder and class streams only overlap on the GPU if each has a hardware
+queue of its own: HIP maps a process's streams onto GPU_MAX_HW_QUEUES queues
+(4 unless set, read when HIP initialises), and streams that share a queue run
+in submission order, so a class would wait behind another stream's builds.
+Start a serving process with at least builders + classes + 1 queues.
 """
 import collections
 import concurrent.futures as cf
+import os
 import threading
 import time
+import warnings
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -65,6 +73,11 @@ class Server:
         self.class_stats = [dict(calls=0, iterations=0, active_sum=0, max_active=0, busy_s=0.0)
                             for _ in self.classes]
         F.faco_set_batch_ants_per_block(ants_per_block)
+        need = builders + len(self.classes) + 1
+        have = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+        if have < need:
+            warnings.warn(f"GPU_MAX_HW_QUEUES={have} < {need}: builder and class streams "
+                          "share hardware queues, and solves wait behind other builds")
         self.build_streams = [torch.cuda.Stream() for _ in range(builders)]
         self.run_streams = [torch.cuda.Stream() for _ in self.classes]
         self.build_q = collections.deque()
