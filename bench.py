@@ -35,13 +35,27 @@ import time
 
 import numpy as np
 
-# The served stream runs two builder streams and three size-class streams
-# beside the library's own.  HIP maps a process's streams onto
-# GPU_MAX_HW_QUEUES hardware queues (4 unless set) and work on streams that
-# share a queue runs in submission order: a class's batches then wait behind
-# another stream's build kernels (up to seconds for a 200k-city initial
-# solution).  HIP reads the setting once, when it initialises.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
+def _run_with_hw_queues(count=16):
+    """The served stream runs two builder streams and three size-class
+    streams beside the library's own.  HIP maps a process's streams onto
+    GPU_MAX_HW_QUEUES hardware queues (4 unless set) and work on streams that
+    share a queue runs in submission order: a class's batches then wait behind
+    another stream's build kernels (up to seconds for a 200k-city initial
+    solution).  HIP takes the setting from the environment the process starts
+    with, so without it the benchmark runs itself as a child process that has
+    it (before anything here touches the GPU) and exits with its status; the
+    child gets SIGTERM if this process ends first."""
+    import signal
+    import subprocess
+
+    def die_with_parent():
+        import ctypes
+        ctypes.CDLL("libc.so.6", use_errno=True).prctl(1, signal.SIGTERM)  # PR_SET_PDEATHSIG
+
+    env = dict(os.environ, GPU_MAX_HW_QUEUES=str(count))
+    return subprocess.run([sys.executable] + sys.argv, env=env,
+                          preexec_fn=die_with_parent).returncode
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -654,4 +668,6 @@ def main():
 
 
 if __name__ == "__main__":
+    if "GPU_MAX_HW_QUEUES" not in os.environ:
+        sys.exit(_run_with_hw_queues())
     main()

@@ -206,9 +206,14 @@ int faco_get_batch_config(faco_batch_config *config);
  * per workgroup for one-wave ants, LDS queue capacity as built or 2048;
  * persistent with 4/8-wave teams; the largest 10/15/20/30% of the instances
  * split off with 4- or 8-wave teams) on twins of the handles built from their
- * own inputs (the handles do not advance); the candidates take turns in three
- * rounds, so each is timed over the same stretch of the twins' run; keeps the
- * fastest, and stores it
+ * own inputs (the handles do not advance).  Each candidate first runs one
+ * untimed iteration (first launches, streams, tables); then, in each of
+ * three rounds (one if trial_iterations < 3) a third of trial_iterations
+ * apart by 5x that many untimed iterations, every device block of the twins
+ * is copied aside and copied back before each candidate's trial, so that all
+ * candidates of a round run the same iterations from the same state (the
+ * copy takes device memory the size of the twins); keeps the fastest total,
+ * and stores it
  * for the batch's size class (the longest tour's power of two): later
  * faco_run_batch calls use the stored configuration of their own class,
  * else of the nearest stored one.  best_out (may be NULL) receives it.  Synchronises hip_stream.

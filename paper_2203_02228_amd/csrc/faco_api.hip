@@ -1324,21 +1324,93 @@ extern "C" int faco_autotune_batch(faco_instance *const *hs, int32_t count,
   if (count >= 4)
     for (int pct : {10, 15, 20, 30})
       for (int btw : {4, 8}) cand.push_back({0, 1, 1, 2048, pct, btw});
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+  // Every device block of the twins is copied aside at the start of a round
+  // and copied back before each candidate's trial, so that all candidates of
+  // a round run the same iterations from the same state.  Rounds lie apart
+  // along the run (the work per iteration changes as it goes), and a
+  // first, untimed pass runs each candidate once (first launches of its
+  // kernels, its streams and tables).
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
     drop();
-    return set_err(nullptr, FACO_EDEVICE, "hipEventCreate failed");
+    return set_err(nullptr, FACO_EDEVICE, "hipGetDevice failed");
   }
-  // The twins advance with every trial, and the work per iteration changes
-  // along a run: the candidates take turns in rounds, so that each is timed
-  // over the same stretch of iterations.
+  std::vector<faco::CopySeg> segs;  // [save..., load...]
+  size_t snap_bytes = 0;
+  for (faco_instance *t : twins)
+    for (auto &a : t->allocs) snap_bytes += (a.second + 255) & ~(size_t)255;
+  void *snap = nullptr, *dsegs = nullptr;
+  size_t snap_got = 0, segs_got = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    blk_put(dev, snap, snap_got);
+    blk_put(dev, dsegs, segs_got);
+    drop();
+  };
+  if (blk_get(dev, snap_bytes, &snap, &snap_got) != hipSuccess) {
+    snap = nullptr;
+    release();
+    return set_err(nullptr, FACO_ENOMEM, "no device memory for the trial snapshot");
+  }
+  {
+    size_t off = 0;
+    for (faco_instance *t : twins)
+      for (auto &a : t->allocs) {
+        segs.push_back({(const unsigned char *)a.first, (unsigned char *)snap + off, a.second});
+        off += (a.second + 255) & ~(size_t)255;
+      }
+    const size_t nseg = segs.size();
+    for (size_t k = 0; k < nseg; ++k)
+      segs.push_back({segs[k].dst, const_cast<unsigned char *>(segs[k].src), segs[k].bytes});
+  }
+  const int nseg = (int)(segs.size() / 2);
+  if (blk_get(dev, sizeof(faco::CopySeg) * segs.size(), &dsegs, &segs_got) != hipSuccess) {
+    dsegs = nullptr;
+    release();
+    return set_err(nullptr, FACO_ENOMEM, "no device memory for the trial snapshot");
+  }
+  const faco::CopySeg *d_save = (const faco::CopySeg *)dsegs, *d_load = d_save + nseg;
+  auto copy = [&](const faco::CopySeg *list) {
+    hipLaunchKernelGGL(faco::copy_segments_kernel, dim3((unsigned)std::min(nseg, 2048)),
+                       dim3(256), 0, st, list, nseg);
+    return hipGetLastError() == hipSuccess ? FACO_OK
+                                           : set_err(nullptr, FACO_EDEVICE, "snapshot copy failed");
+  };
+  if (hipMemcpyAsync(dsegs, segs.data(), sizeof(faco::CopySeg) * segs.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return set_err(nullptr, FACO_EDEVICE, "setting up the trials failed");
+  }
   const int rounds = trial_iterations >= 3 ? 3 : 1;
   std::vector<float> total(cand.size(), 0.0f);
-  int rc = FACO_OK;
+  int rc = copy(d_save);
+  for (size_t ci = 0; ci < cand.size() && rc == FACO_OK; ++ci) {
+    rc = copy(d_load);
+    if (rc == FACO_OK) rc = run_batch_cfg(twins.data(), count, 1, st, cand[ci]);
+  }
+  if (rc == FACO_OK) rc = copy(d_load);
   for (int r = 0; r < rounds && rc == FACO_OK; ++r) {
     const int its = trial_iterations / rounds + (r < trial_iterations % rounds ? 1 : 0);
-    for (size_t ci = 0; ci < cand.size(); ++ci) {
-      if (hipEventRecord(e0, st) != hipSuccess) { rc = FACO_EDEVICE; break; }
+    if (r > 0) {
+      faco_batch_config plain;
+      {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        plain = g_batch_cfg;
+      }
+      rc = run_batch_cfg(twins.data(), count, 5 * its, st, plain);
+    }
+    if (rc == FACO_OK) rc = copy(d_save);
+    for (size_t ci = 0; ci < cand.size() && rc == FACO_OK; ++ci) {
+      rc = copy(d_load);
+      if (rc) break;
+      if (hipEventRecord(e0, st) != hipSuccess) {
+        rc = set_err(nullptr, FACO_EDEVICE, "timing a trial failed");
+        break;
+      }
       rc = run_batch_cfg(twins.data(), count, its, st, cand[ci]);
       if (rc) break;
       float ms = 0.0f;
@@ -1356,9 +1428,7 @@ extern "C" int faco_autotune_batch(faco_instance *const *hs, int32_t count,
       bi = ci;
       best = cand[ci];
     }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  drop();
+  release();
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);

@@ -227,4 +227,27 @@ __global__ void __launch_bounds__(64) knn_kernel(const int2 *xy, const int32_t *
   if (kd[tid] == 0.0) atomicOr(&st->dup, 1);
 }
 
+// ===================================================================== //
+// Device-to-device copies of a list of blocks (the autotuner's snapshot and
+// restore of its trial instances): one workgroup per block at a time, 16-byte
+// words while both addresses are 16-byte aligned, single bytes for the rest.
+// ===================================================================== //
+struct CopySeg {
+  const unsigned char *src;
+  unsigned char *dst;
+  uint64_t bytes;
+};
+
+__global__ void __launch_bounds__(256) copy_segments_kernel(const CopySeg *segs, int nseg) {
+  for (int s = blockIdx.x; s < nseg; s += gridDim.x) {
+    const CopySeg g = segs[s];
+    const bool vec = (((uintptr_t)g.src | (uintptr_t)g.dst) & 15u) == 0;
+    const uint64_t nv = vec ? g.bytes / 16 : 0;
+    const uint4 *sv = reinterpret_cast<const uint4 *>(g.src);
+    uint4 *dv = reinterpret_cast<uint4 *>(g.dst);
+    for (uint64_t k = threadIdx.x; k < nv; k += blockDim.x) dv[k] = sv[k];
+    for (uint64_t k = nv * 16 + threadIdx.x; k < g.bytes; k += blockDim.x) g.dst[k] = g.src[k];
+  }
+}
+
 }  // namespace faco
