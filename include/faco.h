@@ -314,8 +314,12 @@ enum {
                                0 for the ants before the first iteration.
                                A mismatch with the tracked lengths sets a
                                fault.                                         */
-  FACO_DBG_TOUR = 16        /* int64 [3]: segment lists in use (0/1), their
+  FACO_DBG_TOUR = 16,       /* int64 [3]: segment lists in use (0/1), their
                                segment length, the record limit              */
+  FACO_DBG_INIT_TICKS = 17  /* int64 [32]: the initial solution's tick slots
+                               and call counts, as FACO_DBG_PHASE_TICKS for
+                               one ant (slot 4: the whole kernel; set with the
+                               3-opt initial search too, which runs after)   */
 };
 /* device faults (FACO_DBG_FAULT; faco_get_best_tour then returns
  * FACO_EDEVICE) */
@@ -323,6 +327,7 @@ enum {
                                     listed had no move in the evaluation    */
 #define FACO_FAULT_LENGTH 2      /* recomputed length != tracked length      */
 #define FACO_FAULT_PERMUTATION 4 /* an ant route is not a permutation        */
+#define FACO_FAULT_BATCH_STALL 8 /* a persistent batch saw no progress       */
 /* per-ant counters (same meaning as the oracle's) */
 enum {
   FACO_CNT_ACO_STEPS = 0,

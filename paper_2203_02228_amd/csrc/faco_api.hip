@@ -678,6 +678,7 @@ static int fault_error(faco_instance *h, const DevState &hs) {
   if (hs.fault & faco::FAULT_LENGTH)
     what += " a recomputed tour length differs from the tracked one;";
   if (hs.fault & faco::FAULT_PERMUTATION) what += " an ant's route is not a permutation;";
+  if (hs.fault & faco::FAULT_BATCH_STALL) what += " a persistent batch stalled;";
   return set_err(h, FACO_EDEVICE,
                  "device fault" + what + " first at ant " + std::to_string(hs.fault_ant) +
                      " (-1: initial solution or global best), iteration " +
@@ -810,6 +811,11 @@ extern "C" int faco_debug_get(faco_instance *h, int32_t what, void *out, size_t 
       const Inst &I = h->dv;
       int64_t v[3] = {I.seg_on, I.seg_on ? (int64_t)1 << I.seg_shift : 0, I.seg_max};
       std::memcpy(out, v, 24);
+      return FACO_OK;
+    }
+    case FACO_DBG_INIT_TICKS: {
+      if (bytes != 8 * (size_t)faco::kTicks) return set_err(h, FACO_EINVAL, "size mismatch");
+      std::memcpy(out, hs.init_ticks, 8 * (size_t)faco::kTicks);
       return FACO_OK;
     }
     case FACO_DBG_INIT_COUNTERS: {

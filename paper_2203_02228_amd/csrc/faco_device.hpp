@@ -17,6 +17,7 @@ struct DevState {
   int32_t improved;  // 1 if the last iteration improved the global best
   int32_t dup;       // set by the list kernel when two cities coincide
   int64_t init_cnt[13];
+  int64_t init_ticks[32];  // the initial solution's tick slots (an ant's [kTicks])
   // Faults found on the device (FAULT_* bits; the first one's ant and
   // iteration), and the number of tours the verification kernel has checked.
   int32_t fault, fault_ant;
@@ -129,6 +130,8 @@ constexpr int kMaxBl = 64;
 constexpr int kMaxOrSeg = 3;
 // tick and count slots per ant (FACO_DBG_PHASE_TICKS)
 constexpr int kTicks = 32;
+static_assert(sizeof(((DevState *)nullptr)->init_ticks) == sizeof(int64_t) * kTicks,
+              "the initial solution keeps an ant's tick slots");
 // capacity of the segment record table of a segment-list tour
 constexpr int kSegCap = 2048;
 

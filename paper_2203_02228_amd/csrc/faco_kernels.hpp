@@ -2140,6 +2140,8 @@ FACO_DEV void run_ant(const Inst &I, int ant, int mode, uint32_t *lds) {
       I.st->init_len = len;
     }
     if (lane < NCNT) I.st->init_cnt[lane] = cnt.v;
+    tk[4] = ticks() - t0;
+    if (lane < kTicks) I.st->init_ticks[lane] = tk.v;
   } else {
     if (lane == 0) {
       I.lens[ant] = len;

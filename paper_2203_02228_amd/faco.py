@@ -19,7 +19,7 @@ FACO_LS_2OPT, FACO_LS_OROPT, FACO_LS_SWEEP, FACO_LS_INIT_3OPT = 1, 2, 4, 8
  FACO_DBG_LIMITS, FACO_DBG_COUNTERS, FACO_DBG_CAND_LISTS, FACO_DBG_BACKUP_LISTS,
  FACO_DBG_HEURISTIC, FACO_DBG_INFO, FACO_DBG_INIT_COUNTERS,
  FACO_DBG_COUNTER_TOTALS, FACO_DBG_PHASE_TICKS, FACO_DBG_TEAM_WAVES, FACO_DBG_FAULT,
- FACO_DBG_RECOMPUTED_LENGTHS, FACO_DBG_TOUR) = range(17)
+ FACO_DBG_RECOMPUTED_LENGTHS, FACO_DBG_TOUR, FACO_DBG_INIT_TICKS) = range(18)
 FACO_NTICKS = 32  # tick and count slots per ant (FACO_DBG_PHASE_TICKS)
 FACO_FAULT_LS_STALL, FACO_FAULT_LENGTH, FACO_FAULT_PERMUTATION = 1, 2, 4
 CNT_NAMES = ["aco_steps", "copied", "backup", "fallback", "new_edges",
@@ -311,6 +311,7 @@ def faco_debug_get(inst, what):
         FACO_DBG_FAULT: (np.int64, (4,)),
         FACO_DBG_RECOMPUTED_LENGTHS: (np.int64, (A + 1,)),
         FACO_DBG_TOUR: (np.int64, (3,)),
+        FACO_DBG_INIT_TICKS: (np.int64, (FACO_NTICKS,)),
     }
     dt, shape = shapes[what]
     out = np.zeros(shape, dtype=dt)
