@@ -485,7 +485,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=10)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB for resident solves")
     ap.add_argument("--seq-sample", type=int, default=16)
-    ap.add_argument("--served-classes", default="8000,40000",
+    ap.add_argument("--served-classes", default="4000,16000,64000",
                     help="upper size bounds of the served size classes but the last")
     ap.add_argument("--served-builders", type=int, default=2)
     ap.add_argument("--serve-tune", type=int, default=1)

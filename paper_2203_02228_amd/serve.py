@@ -32,7 +32,7 @@ import numpy as np
 from . import faco as F
 
 # upper bounds (exclusive) of the size classes, each with its own worker
-DEFAULT_CLASSES = (8_000, 40_000, 1 << 30)
+DEFAULT_CLASSES = (4_000, 16_000, 64_000, 1 << 30)
 
 
 @dataclass
