@@ -36,14 +36,30 @@ import time
 import numpy as np
 
 
-def _run_with_hw_queues(count=16):
+HW_QUEUES = 16
+
+
+def _needs_hw_queues():
+    """True when this process should run the benchmark as a child with
+    HW_QUEUES hardware queues: the setting is missing or lower (a child never
+    relaunches)."""
+    if os.environ.get("FACO_BENCH_CHILD") == "1":
+        return False
+    try:
+        have = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+    except ValueError:
+        have = 4
+    return have < HW_QUEUES
+
+
+def _run_with_hw_queues(count=HW_QUEUES):
     """The served stream runs two builder streams and three size-class
     streams beside the library's own.  HIP maps a process's streams onto
     GPU_MAX_HW_QUEUES hardware queues (4 unless set) and work on streams that
     share a queue runs in submission order: a class's batches then wait behind
     another stream's build kernels (up to seconds for a 200k-city initial
     solution).  HIP takes the setting from the environment the process starts
-    with, so without it the benchmark runs itself as a child process that has
+    with, so with fewer the benchmark runs itself as a child process that has
     it (before anything here touches the GPU) and exits with its status; the
     child gets SIGTERM if this process ends first."""
     import signal
@@ -53,7 +69,7 @@ def _run_with_hw_queues(count=16):
         import ctypes
         ctypes.CDLL("libc.so.6", use_errno=True).prctl(1, signal.SIGTERM)  # PR_SET_PDEATHSIG
 
-    env = dict(os.environ, GPU_MAX_HW_QUEUES=str(count))
+    env = dict(os.environ, GPU_MAX_HW_QUEUES=str(count), FACO_BENCH_CHILD="1")
     return subprocess.run([sys.executable] + sys.argv, env=env,
                           preexec_fn=die_with_parent).returncode
 
@@ -501,6 +517,7 @@ def main():
                     help="MiB copied once by a plain device-to-device copy kernel before "
                          "the workload (scales hardware byte counters)")
     args = ap.parse_args()
+    log(f"GPU_MAX_HW_QUEUES={os.environ.get('GPU_MAX_HW_QUEUES', '(unset)')}")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the ants of an iteration would shard across GPUs; this benchmark "
@@ -668,6 +685,6 @@ def main():
 
 
 if __name__ == "__main__":
-    if "GPU_MAX_HW_QUEUES" not in os.environ:
+    if _needs_hw_queues():
         sys.exit(_run_with_hw_queues())
     main()

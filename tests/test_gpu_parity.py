@@ -177,3 +177,25 @@ def test_integer_grid(spacing):
         F.faco_run_iterations(g, 1)
         _cmp_iter(o, g, it)
     g.close()
+
+
+def test_build_on_recycled_device_blocks():
+    """Destroyed instances leave their device blocks to the library, and the
+    next builds of similar size take them back with their old contents: an
+    instance built on such blocks still matches the oracle bit for bit."""
+    say("[gpu] recycled blocks: build, run, destroy n=3000, then n=2950 and n=3050")
+    first = F.faco_build_instance(I.make_points("uniform", 3000, 81), n_ants=6, min_new_edges=8)
+    F.faco_run_iterations(first, 4)
+    F.faco_get_best_tour(first)
+    first.close()
+    for n, seed in ((2950, 82), (3050, 83)):
+        xy = I.make_points("cluster16", n, seed)
+        g = F.faco_build_instance(xy, n_ants=6, min_new_edges=8)
+        o = O.Oracle(xy, threads=8, n_ants=6, min_new_edges=8)
+        _cmp_setup(o, g)
+        for it in range(1, 4):
+            o.run(1)
+            F.faco_run_iterations(g, 1)
+            _cmp_iter(o, g, it)
+        g.close()
+        o.close()
