@@ -53,7 +53,7 @@ def _needs_hw_queues():
 
 
 def _run_with_hw_queues(count=HW_QUEUES):
-    """The served stream runs two builder streams and three size-class
+    """The served stream runs three builder streams and four size-class
     streams beside the library's own.  HIP maps a process's streams onto
     GPU_MAX_HW_QUEUES hardware queues (4 unless set) and work on streams that
     share a queue runs in submission order: a class's batches then wait behind
@@ -503,7 +503,7 @@ def main():
     ap.add_argument("--seq-sample", type=int, default=16)
     ap.add_argument("--served-classes", default="4000,16000,64000",
                     help="upper size bounds of the served size classes but the last")
-    ap.add_argument("--served-builders", type=int, default=2)
+    ap.add_argument("--served-builders", type=int, default=3)
     ap.add_argument("--serve-tune", type=int, default=1)
     ap.add_argument("--serve-tune-samples", type=int, default=8,
                     help="requests per size class the served autotune times")

@@ -54,7 +54,7 @@ class Request:
 
 class Server:
     def __init__(self, hbm_budget_bytes=8 << 30, chunk=10, classes=DEFAULT_CLASSES,
-                 builders=2, ants_per_block=1):
+                 builders=3, ants_per_block=1):
         import torch  # streams
         self._torch = torch
         self.budget = int(hbm_budget_bytes)
